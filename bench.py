@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Track-steps/s of the transport iteration on one MI355X.
+
+One benchmark step = one whole run of the workload: inject every primary (already
+resident in device memory) and iterate until no track is left.  The headline
+workload is 10^5 electrons of 10 GeV in one event (seed 7) on the dense double
+buffer with the SoA layout in mixed precision; the same workload is timed
+alongside in FP64 (dense SoA, and the sparse single buffer with the AoS layout,
+the paper's baseline structure), and the per-layer deposit difference between the
+mixed and the FP64 runs is stated.
+
+Prints one JSON line (rank 0).  Only one GPU is used: --gpus above 1 exits.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, AMD's published figure
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--primaries", type=int, default=100_000)
+    ap.add_argument("--capacity-log2", type=int, default=25)
+    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--graph-iters", type=int, default=32)
+    ap.add_argument("--fp64-steps", type=int, default=2, help="timed runs of each FP64 comparison path (0: skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=4800, help="primaries of the workload run by the oracle")
+    ap.add_argument("--headline-only", action="store_true", help="only the headline path (for profilers)")
+    return ap.parse_args()
+
+
+def algorithmic_bytes(st, scheme, precision):
+    """Bytes the method must move for the steps recorded in st (access contract of
+    the track buffers; dense: 13 fields read per source, parentId per survivor,
+    every output written whole; sparse adds the u32 slot-list and ring traffic)."""
+    R = 68 if precision == 1 else 88
+    W = 76 if precision == 1 else 96
+    src = sum(st["track_steps"])
+    surv = sum(st["survivors"])
+    outs = sum(st["outputs"])
+    if scheme == 1:
+        return src * R + surv * 8 + outs * W
+    charged_w = 52 if precision == 1 else 72
+    gamma_w = 40 if precision == 1 else 48
+    surv_w = (st["survivors"][0] + st["survivors"][1]) * charged_w + st["survivors"][2] * gamma_w
+    created = outs - surv
+    killed = src - surv
+    return src * (R + 4) + surv_w + outs * 4 + created * (W + 4) + killed * 4
+
+
+def time_path(ad, torch, wl, dev_prims, scheme, mapping, precision, C, args, steps, warmup, timing):
+    sim = ad.Sim(scheme, mapping, precision, C, 64, seeds=wl.seeds,
+                 launch={"block": args.block, "graph_iters": args.graph_iters})
+    n = len(wl.primaries)
+    for _ in range(warmup):
+        sim.reset()
+        ad.adept_inject_device(sim.ctx, dev_prims.data_ptr(), n)
+        sim.run()
+    total = 0.0
+    per_run = None
+    for k in range(steps):
+        sim.reset()
+        ad.adept_set_timing(sim.ctx, timing)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ad.adept_inject_device(sim.ctx, dev_prims.data_ptr(), n)
+        iters = sim.run()
+        torch.cuda.synchronize()
+        total += time.perf_counter() - t0
+        st = sim.stats()
+        if per_run is None:
+            per_run = dict(st, iterations=iters)
+            per_run["step_kernel_ms"] = 0.0
+            per_run["step_launches"] = 0
+        else:
+            assert st["track_steps"] == per_run["track_steps"], "runs must be identical"
+        per_run["step_kernel_ms"] += st["step_kernel_ms"]
+        per_run["step_launches"] += st["step_launches"]
+    layer = sim.tally(ad.T_LAYER)
+    ein = sim.tally(ad.T_EIN)
+    tot = (sim.tally(ad.T_DEP_CONT).sum() + sim.tally(ad.T_DEP_CUT).sum() + sim.tally(ad.T_ESCAPED).sum()
+           + sim.tally(ad.T_ROUND).sum())
+    closure = abs(ein.sum() - tot) / ein.sum()
+    closure_no_round = abs(ein.sum() - (tot - sim.tally(ad.T_ROUND).sum())) / ein.sum()
+    sim.close()
+    ts = sum(per_run["track_steps"])
+    return {
+        "seconds": total, "ms_per_step": 1e3 * total / steps, "track_steps_per_run": ts,
+        "track_steps_per_s": ts * steps / total, "primaries_per_s": n * steps / total,
+        "iterations": per_run["iterations"], "stats": per_run, "layer": layer, "closure": closure,
+        "closure_without_rounding_ledger": closure_no_round,
+    }
+
+
+def cpu_baseline(wl, sample, precision):
+    """The oracle, unchanged, on a bounded sample of the workload: disjoint chunks of
+    primaries in worker processes (track histories do not depend on batching)."""
+    import multiprocessing as mp
+
+    import oracle
+
+    oracle.build()
+    cores = max(1, min(16, os.cpu_count() or 1))
+    prims = wl.primaries[:sample]
+    chunks = [prims[i::cores] for i in range(cores)]
+    args = [(c, wl.seeds, precision) for c in chunks if len(c)]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(len(args)) as pool:
+        steps = pool.map(_oracle_chunk, args)
+    dt = time.perf_counter() - t0
+    return {"value": sum(steps) / dt, "unit": "track-steps/s", "cores": len(args), "kind": "oracle",
+            "sample": f"first {sample} primaries of the workload, dense double buffer, "
+                      f"{'mixed' if precision else 'FP64'} policy, {sum(steps)} track-steps in {dt:.2f} s wall"}
+
+
+def _oracle_chunk(a):
+    import oracle
+    import workloads
+
+    prims, seeds, precision = a
+    wl = workloads.Workload("chunk", prims, seeds, "")
+    o, rc, _ = oracle.run_workload(wl, oracle.DENSE, precision, 1 << 24)
+    assert rc == 0
+    return sum(o.stats()["track_steps"])
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the transport path shards by events "
+              "with no exchange until a final tally reduction, which this build does not run.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2302_08252_amd as ad
+    import workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    ad.lib()
+    wl = workloads.cfg2(args.primaries)
+    C = 1 << args.capacity_log2
+    dev_prims = torch.from_numpy(wl.primaries.view(np.uint8).copy()).cuda()
+    head = time_path(ad, torch, wl, dev_prims, ad.DENSE_DOUBLE, ad.MAP_SOA, ad.MIXED, C, args, args.steps,
+                     args.warmup, timing=True)
+    st = head["stats"]
+    alg = algorithmic_bytes(st, 1, 1)  # bytes of one run
+    kernel_s = st["step_kernel_ms"] / 1e3
+    achieved = alg * args.steps / kernel_s / 1e9 if kernel_s > 0 else None
+    out = {
+        "metric": "track-steps/sec on 1 MI355X: mixed vs FP64 layout, per-layer Edep error stated",
+        "value": head["track_steps_per_s"],
+        "unit": "track-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64 (mixed)",
+        "data": "synthetic",
+        "config": {
+            "workload": f"1 event x {args.primaries} e- at 10 GeV from (0,0,0) along +z, seed 7; "
+                        "50-layer absorber/gap calorimeter; all primaries injected at once",
+            "scheme": "dense double buffer", "layout": "SoA", "precision": "mixed",
+            "capacity_per_type": C, "block": args.block, "graph_iters": args.graph_iters,
+        },
+        "primaries_per_s": head["primaries_per_s"],
+        "track_steps_per_run": head["track_steps_per_run"],
+        "iterations_per_run": head["iterations"],
+        "divergent_wave_fraction": st["waves_divergent"] / max(st["waves"], 1),
+        "closure_error": head["closure"],
+        "roofline": {
+            "bound": "hbm", "kernel": "k_step (fused transport step)",
+            "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": (achieved / PEAK_HBM_GBS) if achieved else None,
+            "traffic": None,
+            "algorithmic_bytes_per_run": alg,
+            "step_launches_timed": st["step_launches"],
+            "avg_step_kernel_ms": st["step_kernel_ms"] / max(st["step_launches"], 1),
+        },
+    }
+    if not args.headline_only and args.fp64_steps > 0:
+        f64 = time_path(ad, torch, wl, dev_prims, ad.DENSE_DOUBLE, ad.MAP_SOA, ad.FP64, C, args, args.fp64_steps,
+                        1, timing=False)
+        sp = time_path(ad, torch, wl, dev_prims, ad.SPARSE_SINGLE, ad.MAP_AOS, ad.FP64, C, args, args.fp64_steps,
+                       1, timing=False)
+        lm, lf = head["layer"], f64["layer"]
+        rel = np.abs(lm - lf) / np.maximum(np.abs(lf), 1e-300)
+        assert np.array_equal(lf, sp["layer"]) or np.allclose(lf, sp["layer"], rtol=1e-12)
+        out["fp64_dense_soa"] = {"track_steps_per_s": f64["track_steps_per_s"], "ms_per_step": f64["ms_per_step"],
+                                 "closure_error": f64["closure"]}
+        out["fp64_sparse_aos"] = {"track_steps_per_s": sp["track_steps_per_s"], "ms_per_step": sp["ms_per_step"],
+                                  "closure_error": sp["closure"]}
+        out["speedup_vs_fp64_sparse_aos"] = sp["ms_per_step"] / head["ms_per_step"]
+        out["edep_per_layer_rel_error_mixed_vs_fp64"] = {
+            "max": float(rel.max()), "max_over_layers_above_1e-3_of_total": float(rel[lf > 1e-3 * lf.sum()].max()),
+            "total": float(abs(lm.sum() - lf.sum()) / lf.sum()),
+            "reference": "the same workload in FP64 on the GPU (bit-exact with the FP64 oracle per track)",
+        }
+    if not args.headline_only and not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample, 1)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

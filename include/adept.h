@@ -1,0 +1,241 @@
+/*
+ * adept.h -- C ABI of the MI355X (gfx950) track-transport library.
+ *
+ * The library runs the per-iteration transport step of the paper "Challenges
+ * and opportunities integrating LLAMA into AdePT" (arXiv 2302.08252) on one
+ * GPU: every active electron, positron and photon track is loaded through a
+ * switchable record layout (Sec. 3-4: AoS, SoA, AoSoA-N) from one of the two
+ * track data structures of Sec. 2 (the sparse single buffer with slot lists,
+ * or the dense double buffer), stepped once through a seeded toy
+ * electromagnetic shower in a 50-layer absorber/gap calorimeter, and written
+ * with its secondaries into the next iteration's buffer by ordered stream
+ * compaction.  An instrumented mode counts field reads and writes and builds
+ * per-byte heatmaps of the track buffers (Sec. 5).
+ *
+ * Conventions
+ *  - Every function returns adept_status: 0 on success, a negative code on error.
+ *  - Host arrays belong to the caller; inputs are copied in before return,
+ *    outputs are copied out into caller buffers.  Out-parameters are written
+ *    only on success.
+ *  - Device memory: either the caller hands in an arena (adept_bind, a device
+ *    pointer and size, kept alive by the caller) or the library allocates one
+ *    at the first call that needs it.  Either way all work is enqueued on one
+ *    HIP stream (the caller's, if bound).  A context is not thread-safe.
+ *  - After ADEPT_E_CAPACITY or ADEPT_E_DEVICE the context is failed: only
+ *    adept_tally, adept_stats, adept_dump_tracks, adept_last_error and
+ *    adept_destroy remain valid.
+ *  - Units: mm and MeV.
+ */
+#ifndef ADEPT_H
+#define ADEPT_H
+#include <stddef.h>
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t adept_status;
+enum {
+  ADEPT_OK = 0,
+  ADEPT_E_INVALID = -1,     /* bad argument (range, NaN, unknown enum, wrong size)   */
+  ADEPT_E_CAPACITY = -2,    /* a buffer overflowed; the iteration is in adept_stats   */
+  ADEPT_E_DEVICE = -3,      /* a HIP call failed; see adept_last_error                */
+  ADEPT_E_STATE = -4,       /* call not allowed in the context's current state        */
+  ADEPT_E_NOMEM = -5,       /* allocation failed or the bound arena is too small      */
+  ADEPT_E_UNSUPPORTED = -6  /* option not available in this build                     */
+};
+
+typedef struct adept_ctx adept_ctx; /* opaque, owned by the library */
+
+/* Sec. 2: sparse single buffer (slot array + current/next slot lists, free
+ * slots recycled through a FIFO ring) or dense double buffer (two dense
+ * arrays per particle type, swapped every iteration). */
+typedef enum { ADEPT_SPARSE_SINGLE = 0, ADEPT_DENSE_DOUBLE = 1 } adept_scheme;
+/* Sec. 3-4: record layouts. */
+typedef enum { ADEPT_MAP_AOS = 0, ADEPT_MAP_SOA = 1, ADEPT_MAP_AOSOA = 2 } adept_mapping;
+typedef struct {
+  int32_t scheme;       /* adept_scheme                                  */
+  int32_t mapping;      /* adept_mapping                                 */
+  uint32_t aosoa_lanes; /* AoSoA lanes N: a power of two in [2, 256]     */
+} adept_layout;
+
+/* FP64: all track arithmetic in binary64.  MIXED: direction, energy and
+ * interaction length stored and stepped in binary32; position, boundary
+ * distance and energy tallies stay binary64. */
+typedef enum { ADEPT_FP64 = 0, ADEPT_MIXED = 1 } adept_precision;
+typedef enum { ADEPT_ELECTRON = 0, ADEPT_POSITRON = 1, ADEPT_GAMMA = 2 } adept_particle;
+
+typedef enum {
+  ADEPT_T_DEP_CONT = 0, /* [event][volume 0..99] continuous-loss deposits            */
+  ADEPT_T_DEP_CUT = 1,  /* [event][volume 0..99] local (below-cut) deposits          */
+  ADEPT_T_LAYER = 2,    /* [event][layer 0..49] = continuous + local, both volumes    */
+  ADEPT_T_ESCAPED = 3,  /* [event] energy leaving the calorimeter (+ 2 m_e per e+)   */
+  ADEPT_T_ROUND = 4,    /* [event] exact rounding residuals of the energy ledger     */
+  ADEPT_T_INFLIGHT = 5, /* [event] energy of buffered tracks (+ 2 m_e per e+)        */
+  ADEPT_T_CELLS = 6,    /* [layer][ix][iy] deposits summed over events (scoring on)  */
+  ADEPT_T_EIN = 7       /* [event] primary energy injected (+ 2 m_e per e+)          */
+} adept_tally_kind;
+
+/* A primary (80 bytes).  event indexes the table of adept_set_events (0 if none
+ * was set); type is an adept_particle; E finite and > 0; pos inside the
+ * calorimeter (0 <= z < 400, |x|, |y| <= 200); dir used as given; numIALeft < 0
+ * means "sample at the first step", >= 0 forces it; trackId < 2^63, unique in
+ * its event. */
+typedef struct {
+  uint32_t event;
+  int32_t type;
+  double E;
+  double pos[3];
+  double dir[3];
+  double numIALeft;
+  uint64_t trackId;
+} adept_primary;
+
+/* A track as returned by adept_dump_tracks (96 bytes, values widened to double). */
+typedef struct {
+  double pos[3];
+  double dir[3];
+  double E;
+  double numIALeft;
+  uint64_t trackId;
+  uint64_t parentId;
+  uint32_t rngSeed;
+  uint32_t rngCtr;
+  int32_t volume;
+  uint32_t event;
+} adept_track_host;
+
+typedef struct {
+  uint64_t iterations;       /* iterations done                                      */
+  uint64_t track_steps[3];   /* step-function executions per source type            */
+  uint64_t peak[3];          /* largest active count per type at an iteration start */
+  uint64_t counts[3];        /* current active counts                                */
+  uint64_t error_iter;       /* iteration at which a capacity overflow latched (0)  */
+  uint64_t survivors[3];     /* source tracks that survived their step, per type     */
+  uint64_t outputs[3];       /* tracks written into next buffers (survivors +
+                                buffered creations), per type                        */
+  double step_kernel_ms;     /* summed step-kernel time of timed runs (adept_set_timing) */
+  uint64_t step_launches;    /* step-kernel launches those milliseconds cover        */
+  uint64_t waves;            /* wavefronts that stepped tracks                       */
+  uint64_t waves_divergent;  /* ... whose lanes disagreed on the step limiter or the
+                                interaction outcome (divergence diagnostic)          */
+  int32_t status;            /* ADEPT_OK or the latched error                        */
+  int32_t pad;
+} adept_stats;
+
+/* Launch configuration (autotuner output; also settable by hand). */
+typedef struct {
+  uint32_t block;       /* threads per block = compaction tile: 64, 128 or 256   */
+  uint32_t grid;        /* resident blocks (0: library default)                  */
+  uint32_t graph_iters; /* iterations captured per hipGraph replay (1..256)      */
+  uint32_t pad;
+} adept_launch;
+
+/* Create a context.  capacity = slots per particle type and per buffer, in
+ * [1, 2^30]; for AoSoA a multiple of aosoa_lanes.  The layout, precision and
+ * capacity are fixed for the context's lifetime.  Errors: ADEPT_E_INVALID. */
+adept_status adept_create(adept_layout layout, adept_precision precision, uint64_t capacity, adept_ctx** out);
+
+/* Device bytes the context needs with its current settings (events, scoring,
+ * instrumentation).  Valid before adept_bind. */
+adept_status adept_arena_bytes(const adept_ctx* ctx, size_t* bytes);
+
+/* Hand in a caller-owned device arena (256-byte aligned, >= adept_arena_bytes)
+ * and the HIP stream (hipStream_t, may be NULL for the null stream) on which
+ * all work is enqueued.  Must come before the first inject.  The caller keeps
+ * both alive until adept_destroy.  Errors: ADEPT_E_NOMEM (too small),
+ * ADEPT_E_STATE (already bound or allocated). */
+adept_status adept_bind(adept_ctx* ctx, void* dev_arena, size_t bytes, void* hip_stream);
+
+/* Per-event seeds (copied); default is one event with seed 1.  Before bind. */
+adept_status adept_set_events(adept_ctx* ctx, uint32_t n_events, const uint32_t* seeds);
+
+/* Per-cell deposit tally: each layer split into nx x ny cells of pitch mm,
+ * centred on the beam axis.  Before bind. */
+adept_status adept_set_scoring(adept_ctx* ctx, uint32_t nx, uint32_t ny, double pitch_mm);
+
+/* Event admission (before each iteration, whole events in order while
+ * n_type + ceil(kappa_type * E_event / 1000) <= alpha * capacity for every
+ * type; the first waiting event is always admitted when no track is active).
+ * When on, adept_inject stages primaries instead of injecting them. */
+adept_status adept_set_admission(adept_ctx* ctx, int on, double alpha, const double kappa[3]);
+
+/* Instrumented mode (Sec. 5): count field reads/writes and per-word accesses
+ * of every operation that starts while fewer than last_iter iterations are
+ * done.  Before bind. */
+adept_status adept_set_instrumented(adept_ctx* ctx, int on, uint64_t last_iter);
+
+/* Launch configuration; invalidates the captured graph. */
+adept_status adept_set_launch(adept_ctx* ctx, const adept_launch* launch);
+adept_status adept_get_launch(const adept_ctx* ctx, adept_launch* launch);
+
+/* Primaries (copied).  Without admission they pass through the creation path
+ * at once, in input order, appended after the current tracks of their type;
+ * with admission they must be grouped by non-decreasing event and wait to be
+ * admitted (staging is only allowed before the first iteration).  Errors: ADEPT_E_INVALID (bad primary; nothing is injected),
+ * ADEPT_E_CAPACITY. */
+adept_status adept_inject(adept_ctx* ctx, const adept_primary* p, uint64_t n);
+
+/* As adept_inject, for primaries already in device memory (80-byte records
+ * at dev_p, owned by the caller, read before return).  They are checked on the
+ * device; any invalid primary fails the call with nothing injected.  Not
+ * available with admission (ADEPT_E_UNSUPPORTED). */
+adept_status adept_inject_device(adept_ctx* ctx, const adept_primary* dev_p, uint64_t n);
+
+/* Exactly one iteration (admission, then one step of every active track);
+ * synchronous; next_counts (nullable) receives the active counts per type. */
+adept_status adept_step(adept_ctx* ctx, uint64_t next_counts[3]);
+
+/* Iterate until no track is active and nothing is staged, or max_iter
+ * iterations; iterations replay a captured hipGraph of graph_iters iterations.
+ * iters_done (nullable) receives the iterations done by this call. */
+adept_status adept_run(adept_ctx* ctx, uint64_t max_iter, uint64_t* iters_done);
+
+/* Copy a tally out; n must equal the kind's size (see adept_tally_kind). */
+adept_status adept_tally(adept_ctx* ctx, adept_tally_kind kind, double* out, size_t n);
+
+/* Access counts of one physical buffer (buffer 0, or 1 = second dense array):
+ * reads/writes per field (14 each, nullable) and, if heat_words is not NULL,
+ * the per-4-byte-word access counters (n_words must equal the buffer size / 4). */
+adept_status adept_access_counts(adept_ctx* ctx, adept_particle t, uint32_t buffer, uint64_t reads[14],
+                                 uint64_t writes[14], uint32_t* heat_words, size_t n_words);
+
+/* Byte size of one physical track buffer of this context. */
+adept_status adept_buffer_bytes(const adept_ctx* ctx, size_t* bytes);
+
+adept_status adept_stats_get(adept_ctx* ctx, adept_stats* out);
+
+/* The current tracks of one type in current order (dense: array order; sparse:
+ * slot-list order) with their slot numbers (slots nullable).  Debug/parity. */
+adept_status adept_dump_tracks(adept_ctx* ctx, adept_particle t, adept_track_host* out, uint32_t* slots,
+                               uint64_t cap, uint64_t* n);
+
+/* Sparse scheme: the free-slot ring of one type, its head and free count. */
+adept_status adept_dump_ring(adept_ctx* ctx, adept_particle t, uint32_t* ring, uint64_t cap, uint64_t* head,
+                             uint64_t* count);
+
+/* Reset to the state right after creation+bind (tracks, ring, tallies,
+ * counters, staged primaries) without reallocating. */
+adept_status adept_reset(adept_ctx* ctx);
+
+/* Pick the launch configuration (block size = compaction tile, grid, graph
+ * iterations) for this context by timing short runs of the given primaries on
+ * scratch state; the context is reset afterwards.  Ties go to the smaller
+ * block.  result (nullable) receives the choice. */
+adept_status adept_autotune(adept_ctx* ctx, const adept_primary* p, uint64_t n, adept_launch* result);
+
+/* Timed mode for measurements: adept_run launches iterations one by one with
+ * HIP events around every step kernel and accumulates their durations into
+ * adept_stats (step_kernel_ms, step_launches); resets the accumulators. */
+adept_status adept_set_timing(adept_ctx* ctx, int on);
+
+/* Last error message of this context (valid until the next call on it). */
+const char* adept_last_error(const adept_ctx* ctx);
+
+/* Destroy the context (accepts NULL); frees library-owned memory only. */
+void adept_destroy(adept_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

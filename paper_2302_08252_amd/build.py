@@ -1,0 +1,62 @@
+"""Build libadept.so (HIP for gfx950) in-tree with hipcc.
+
+Every translation unit is compiled with -ffp-contract=off (no FMA contraction,
+so binary64/binary32 results follow source order) and with packed-FP32
+instructions disabled.
+"""
+import concurrent.futures
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libadept.so")
+ARCH = os.environ.get("ADEPT_OFFLOAD_ARCH", "gfx950")
+
+SOURCES = ["capi.hip", "inst_dense_f64.hip", "inst_dense_mixed.hip", "inst_sparse_f64.hip", "inst_sparse_mixed.hip"]
+HEADERS = ["kernels.hpp", "layout.hpp", "model.hpp", os.path.join("..", "..", "include", "adept.h")]
+FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-munsafe-fp-atomics",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-function",
+]
+
+
+def _newest(paths):
+    return max(os.path.getmtime(p) for p in paths)
+
+
+def build(force=True, jobs=None, verbose=False):
+    """Compile every HIP translation unit and link libadept.so.  With force=False
+    an up-to-date library is kept."""
+    os.makedirs(BUILD, exist_ok=True)
+    hdr = _newest([os.path.join(CSRC, h) for h in HEADERS])
+    if not force and os.path.exists(LIB):
+        if os.path.getmtime(LIB) >= max(hdr, _newest([os.path.join(CSRC, s) for s in SOURCES])):
+            return LIB
+
+    def compile_one(src):
+        obj = os.path.join(BUILD, src.replace(".hip", ".o"))
+        cmd = ["hipcc", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True, cwd=BUILD)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+        if verbose:
+            sys.stderr.write(r.stderr)
+        return obj
+
+    jobs = jobs or min(len(SOURCES), os.cpu_count() or 1)
+    with concurrent.futures.ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(compile_one, SOURCES))
+    tmp = LIB + ".tmp"
+    r = subprocess.run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs],
+                       capture_output=True, text=True, cwd=BUILD)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stderr}")
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(force="--if-stale" not in sys.argv, verbose="-v" in sys.argv))

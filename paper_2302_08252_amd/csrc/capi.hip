@@ -1,0 +1,1005 @@
+// capi.hip -- the C ABI of include/adept.h: context, arena layout, launch
+// sequences (per-iteration launches and hipGraph replay), readback.
+//
+// Per iteration the stream sees
+//   [k_admit, k_inject, k_inject_epi]   (only with event admission)
+//   k_step                               (fixed grid, tile tickets, look-back)
+//   k_epilogue                           (one wavefront)
+// and adept_run captures graph_iters such iterations into one hipGraph that it
+// replays until the host-mapped mirror reports that nothing is left.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+using namespace adept;
+
+namespace {
+
+enum State { CREATED = 0, READY = 1, FAILED = 2 };
+
+// ---------------------------------------------------------------------------
+// Small kernels
+// ---------------------------------------------------------------------------
+__global__ void k_epilogue(const KArgs a) {
+  if (threadIdx.x != 0) return;
+  Ctrl* c = a.ctrl;
+  HostMirror* m = a.mirror;
+  if (c->error) return;
+  const uint32_t p = c->parity;
+  const unsigned long long sum = c->n[p][0] + c->n[p][1] + c->n[p][2];
+  const bool staged_left = a.adm_on && c->next_group < c->n_groups;
+  const bool live = sum > 0 || (a.adm_on && c->had_staged);
+  if (!live && !a.count_empty) {
+    m->done = staged_left ? 0ull : 1ull;
+    return;
+  }
+  unsigned long long tot[9];
+  for (int v = 0; v < 9; ++v) tot[v] = sum == 0 ? 0ull : c->tot[p][v];
+  const unsigned long long it = c->iter + 1;
+  bool ovf = c->overflow != 0;
+  for (int d = 0; d < 3; ++d) {
+    if (a.scheme == DENSE) ovf = ovf || tot[d] > a.C;
+    else ovf = ovf || tot[3 + d] > c->count[d] || tot[d] > a.C;
+  }
+  if (c->overflow & 2ull) {  // a look-back wait gave up: the state is unusable
+    c->error = ADEPT_E_DEVICE;
+    c->error_iter = it;
+    m->error = ADEPT_E_DEVICE;
+    m->error_iter = it;
+    m->done = 1;
+    return;
+  }
+  if (ovf) {
+    c->error = ADEPT_E_CAPACITY;
+    c->error_iter = it;
+    m->error = ADEPT_E_CAPACITY;
+    m->error_iter = it;
+    m->done = 1;
+    return;
+  }
+  for (int d = 0; d < 3; ++d) {
+    c->steps[d] += c->n[p][d];
+    c->outputs[d] += tot[d];
+    if (c->n[p][d] > c->peak[d]) c->peak[d] = c->n[p][d];
+    c->n[1 - p][d] = tot[d];
+    if (a.scheme == SPARSE) {
+      c->head[d] = (c->head[d] + tot[3 + d]) % a.C;
+      c->count[d] = c->count[d] - tot[3 + d] + tot[6 + d];
+    }
+  }
+  c->parity = 1 - p;
+  c->iter = it;
+  m->iter = it;
+  for (int d = 0; d < 3; ++d) m->n[d] = tot[d];
+  m->done = (tot[0] + tot[1] + tot[2] == 0 && !staged_left) ? 1ull : 0ull;
+}
+
+// Event admission before an iteration (one thread; binary64 arithmetic).
+__global__ void k_admit(const KArgs a) {
+  if (threadIdx.x != 0) return;
+  Ctrl* c = a.ctrl;
+  c->inj_begin = c->inj_end = 0;
+  if (c->error) return;
+  const uint32_t p = c->parity;
+  c->had_staged = c->next_group < c->n_groups ? 1u : 0u;
+  if (!c->had_staged) return;
+  double run[3] = {(double)c->n[p][0], (double)c->n[p][1], (double)c->n[p][2]};
+  const bool none_active = c->n[p][0] + c->n[p][1] + c->n[p][2] == 0;
+  const double limit = a.alpha * (double)a.C;
+  const unsigned long long g0 = c->next_group;
+  unsigned long long g = g0;
+  while (g < c->n_groups) {
+    double need[3];
+    bool fits = true;
+    for (int d = 0; d < 3; ++d) {
+      need[d] = ceil(a.kappa[d] * a.groups[g].energy / 1000.0);
+      if (!(run[d] + need[d] <= limit)) fits = false;
+    }
+    if (!fits && !(none_active && g == g0)) break;
+    for (int d = 0; d < 3; ++d) run[d] = run[d] + need[d];
+    g += 1;
+  }
+  if (g > g0) {
+    c->inj_begin = a.groups[g0].first;
+    c->inj_end = a.groups[g - 1].first + a.groups[g - 1].count;
+    c->next_group = g;
+  }
+}
+
+__global__ void k_set_range(const KArgs a, unsigned long long begin, unsigned long long end) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    a.ctrl->inj_begin = begin;
+    a.ctrl->inj_end = a.ctrl->error ? begin : end;
+  }
+}
+
+__global__ void k_inject_epi(const KArgs a) {
+  if (threadIdx.x != 0) return;
+  Ctrl* c = a.ctrl;
+  HostMirror* m = a.mirror;
+  const uint32_t p = c->parity;
+  c->inj_parity ^= 1u;
+  if (c->error) return;
+  const unsigned long long cnt = c->inj_end - c->inj_begin;
+  bool ovf = c->overflow != 0;
+  unsigned long long tot[3];
+  for (int d = 0; d < 3; ++d) {
+    tot[d] = cnt == 0 ? 0ull : c->inj_tot[d];
+    if (a.scheme == DENSE) ovf = ovf || c->n[p][d] + tot[d] > a.C;
+    else ovf = ovf || tot[d] > c->count[d];
+  }
+  if (ovf) {
+    c->error = ADEPT_E_CAPACITY;
+    c->error_iter = c->iter + 1;
+    m->error = ADEPT_E_CAPACITY;
+    m->error_iter = c->iter + 1;
+    m->done = 1;
+    return;
+  }
+  for (int d = 0; d < 3; ++d) {
+    c->n[p][d] += tot[d];
+    if (a.scheme == SPARSE) {
+      c->head[d] = (c->head[d] + tot[d]) % a.C;
+      c->count[d] -= tot[d];
+    }
+    m->n[d] = c->n[p][d];
+  }
+  m->done = 0;
+}
+
+// Primaries in device memory are checked before injection; any invalid one
+// empties the injection range and is counted.
+__global__ void k_validate(const KArgs a, const adept_primary* p, unsigned long long n, unsigned long long* bad) {
+  const unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const adept_primary q = p[i];
+  bool ok = q.type >= 0 && q.type <= 2 && q.event < a.n_events && isfinite(q.E) && q.E > 0.0 &&
+            isfinite(q.numIALeft) && (q.trackId >> 63) == 0;
+  for (int k = 0; k < 3; ++k) ok = ok && isfinite(q.pos[k]) && isfinite(q.dir[k]);
+  ok = ok && q.pos[2] >= 0.0 && q.pos[2] < 400.0 && fabs(q.pos[0]) <= 200.0 && fabs(q.pos[1]) <= 200.0;
+  if (!ok) atomicAdd(bad, 1ull);
+}
+
+__global__ void k_group_energy(EventGroup* g, const adept_primary* p, unsigned long long n_groups) {
+  const unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_groups) return;
+  double e = 0.0;
+  for (unsigned long long k = 0; k < g[i].count; ++k) e = e + p[g[i].first + k].E;
+  g[i].energy = e;
+}
+
+__global__ void k_layer(const KArgs a, double* out) {
+  const unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (unsigned long long)a.n_events * kNumLayer) return;
+  const unsigned long long e = i / kNumLayer, l = i % kNumLayer;
+  const double* ct = a.cont + e * kNumVol + 2 * l;
+  const double* cu = a.cut + e * kNumVol + 2 * l;
+  out[i] = ((ct[0] + ct[1]) + cu[0]) + cu[1];
+}
+
+// Reset: clear the look-back words still in use, refill the free rings.
+__global__ void k_reset(const KArgs a, unsigned long long step_words0, unsigned long long step_words1,
+                        unsigned long long inj_words0, unsigned long long inj_words1) {
+  const unsigned long long g = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+  for (unsigned long long i = g; i < step_words0; i += stride) a.desc[0][i] = 0;
+  for (unsigned long long i = g; i < step_words1; i += stride) a.desc[1][i] = 0;
+  for (unsigned long long i = g; i < inj_words0; i += stride) a.idesc[0][i] = 0;
+  for (unsigned long long i = g; i < inj_words1; i += stride) a.idesc[1][i] = 0;
+  if (a.scheme == SPARSE)
+    for (int d = 0; d < 3; ++d)
+      for (unsigned long long i = g; i < a.C; i += stride) a.ring[d][i] = (uint32_t)i;
+}
+
+__global__ void k_ctrl_init(const KArgs a) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  Ctrl* c = a.ctrl;
+  memset(c, 0, sizeof(Ctrl));
+  for (int d = 0; d < 3; ++d) c->count[d] = a.scheme == SPARSE ? a.C : 0ull;
+  HostMirror* m = a.mirror;
+  memset(m, 0, sizeof(HostMirror));
+  m->done = 1;
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+Ops g_ops[2][2][3][2];  // [scheme][precision][map][instr]
+bool g_ops_ready = false;
+
+void init_ops() {
+  if (g_ops_ready) return;
+  ops_sparse_f64(g_ops[SPARSE][0]);
+  ops_sparse_mixed(g_ops[SPARSE][1]);
+  ops_dense_f64(g_ops[DENSE][0]);
+  ops_dense_mixed(g_ops[DENSE][1]);
+  g_ops_ready = true;
+}
+
+}  // namespace
+
+struct adept_ctx {
+  adept_layout layout{};
+  int prec = 0;
+  unsigned long long C = 0;
+  int state = CREATED;
+  std::string err;
+  // configuration
+  std::vector<uint32_t> seeds{1u};
+  uint32_t nx = 0, ny = 0;
+  double pitch = 0.0;
+  int adm_on = 0;
+  double alpha = 0.8, kappa[3] = {0, 0, 0};
+  int instr_on = 0;
+  unsigned long long instr_last = 0;
+  adept_launch launch{256, 0, 32, 0};
+  // device
+  int device = 0, num_cu = 0;
+  void* arena = nullptr;
+  size_t arena_size = 0;
+  bool own_arena = false;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  hipStream_t cap_stream = nullptr;
+  HostMirror* mirror = nullptr;
+  KArgs args{};
+  uint64_t buf_bytes = 0;
+  // staged primaries (library-owned device memory)
+  adept_primary* staged = nullptr;
+  unsigned long long staged_cap = 0;
+  EventGroup* groups = nullptr;
+  unsigned long long groups_cap = 0;
+  std::vector<adept_primary> host_staged;
+  bool staged_dirty = false;
+  bool admission_started = false;
+  unsigned long long* dev_bad = nullptr;
+  double* scratch = nullptr;  // readback scratch (n_events * 100 or cells)
+  // per-launch timing of the step kernel (adept_set_timing)
+  int timing = 0;
+  std::vector<hipEvent_t> ev;
+  double step_ms = 0.0;
+  unsigned long long step_launches = 0;
+  // graph
+  hipGraphExec_t graph = nullptr;
+  bool graph_valid = false;
+  unsigned graph_k = 0;
+};
+
+namespace {
+
+adept_status fail(adept_ctx* c, adept_status code, const std::string& msg) {
+  c->err = msg;
+  if (code == ADEPT_E_DEVICE || code == ADEPT_E_CAPACITY) c->state = FAILED;
+  return code;
+}
+
+#define HIPCHK(call)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) return fail(c, ADEPT_E_DEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+struct Plan {
+  size_t ctrl, buf[3][2], list[3][2], ring[3], desc[2], idesc[2], cont, cut, esc, rnd, ein, cells, scratch, rw,
+      heat[3][2], seeds, total;
+  unsigned long long desc_words, idesc_words;
+};
+
+size_t bump(size_t& at, size_t bytes) {
+  const size_t o = at;
+  at = align256(at + bytes);
+  return o;
+}
+
+uint64_t buf_bytes_of(const adept_ctx* c) {
+  return c->prec ? buffer_bytes<true>(c->layout.mapping, c->layout.aosoa_lanes, c->C)
+                 : buffer_bytes<false>(c->layout.mapping, c->layout.aosoa_lanes, c->C);
+}
+
+Plan plan(const adept_ctx* c) {
+  Plan P{};
+  size_t at = 0;
+  const bool dense = c->layout.scheme == ADEPT_DENSE_DOUBLE;
+  const uint64_t bb = buf_bytes_of(c);
+  const unsigned long long E = c->seeds.size();
+  P.ctrl = bump(at, sizeof(Ctrl));
+  for (int t = 0; t < 3; ++t)
+    for (int b = 0; b < 2; ++b) P.buf[t][b] = (b == 0 || dense) ? bump(at, bb) : 0;
+  for (int t = 0; t < 3; ++t) {
+    for (int b = 0; b < 2; ++b) P.list[t][b] = dense ? 0 : bump(at, c->C * 4);
+    P.ring[t] = dense ? 0 : bump(at, c->C * 4);
+  }
+  const unsigned long long max_tiles = (3 * c->C + 63) / 64 + 3;
+  P.desc_words = max_tiles * (dense ? 3 : 9);
+  P.idesc_words = max_tiles * 3;
+  for (int q = 0; q < 2; ++q) P.desc[q] = bump(at, P.desc_words * 8);
+  for (int q = 0; q < 2; ++q) P.idesc[q] = bump(at, P.idesc_words * 8);
+  P.cont = bump(at, E * kNumVol * 8);
+  P.cut = bump(at, E * kNumVol * 8);
+  P.esc = bump(at, E * 8);
+  P.rnd = bump(at, E * 8);
+  P.ein = bump(at, E * 8);
+  const size_t ncell = (size_t)kNumLayer * c->nx * c->ny;
+  P.cells = ncell ? bump(at, ncell * 8) : 0;
+  P.scratch = bump(at, std::max<size_t>(E * kNumVol, ncell) * 8 + 8);
+  P.rw = bump(at, 3 * 2 * 28 * 8);
+  for (int t = 0; t < 3; ++t)
+    for (int b = 0; b < 2; ++b) P.heat[t][b] = (c->instr_on && (b == 0 || dense)) ? bump(at, bb) : 0;
+  P.seeds = bump(at, E * 4);
+  P.total = at;
+  return P;
+}
+
+void fill_args(adept_ctx* c) {
+  const Plan P = plan(c);
+  uint8_t* A = (uint8_t*)c->arena;
+  const bool dense = c->layout.scheme == ADEPT_DENSE_DOUBLE;
+  KArgs& a = c->args;
+  a = KArgs{};
+  a.ctrl = (Ctrl*)(A + P.ctrl);
+  a.mirror = c->mirror;
+  for (int t = 0; t < 3; ++t) {
+    for (int b = 0; b < 2; ++b) {
+      a.buf[t][b] = (b == 0 || dense) ? A + P.buf[t][b] : nullptr;
+      a.list[t][b] = dense ? nullptr : (uint32_t*)(A + P.list[t][b]);
+      a.rw[t][b] = (unsigned long long*)(A + P.rw) + (t * 2 + b) * 28;
+      a.heat[t][b] = P.heat[t][b] ? (uint32_t*)(A + P.heat[t][b]) : nullptr;
+    }
+    a.ring[t] = dense ? nullptr : (uint32_t*)(A + P.ring[t]);
+  }
+  for (int q = 0; q < 2; ++q) {
+    a.desc[q] = (unsigned long long*)(A + P.desc[q]);
+    a.idesc[q] = (unsigned long long*)(A + P.idesc[q]);
+  }
+  a.cont = (double*)(A + P.cont);
+  a.cut = (double*)(A + P.cut);
+  a.esc = (double*)(A + P.esc);
+  a.rnd = (double*)(A + P.rnd);
+  a.ein = (double*)(A + P.ein);
+  a.cells = P.cells ? (double*)(A + P.cells) : nullptr;
+  a.nx = c->nx;
+  a.ny = c->ny;
+  a.pitch = c->pitch;
+  a.staged = c->staged;
+  a.groups = c->groups;
+  a.seeds = (const uint32_t*)(A + P.seeds);
+  a.n_events = (uint32_t)c->seeds.size();
+  a.scheme = c->layout.scheme;
+  a.C = c->C;
+  a.map = c->prec ? make_map_args<true>(c->layout.mapping, c->layout.aosoa_lanes, c->C)
+                  : make_map_args<false>(c->layout.mapping, c->layout.aosoa_lanes, c->C);
+  a.instr_last = c->instr_last;
+  a.instr_on = c->instr_on;
+  a.adm_on = c->adm_on;
+  a.alpha = c->alpha;
+  for (int d = 0; d < 3; ++d) a.kappa[d] = c->kappa[d];
+  a.count_empty = 1;
+  c->scratch = (double*)(A + P.scratch);
+  c->buf_bytes = buf_bytes_of(c);
+}
+
+const Ops& ops(const adept_ctx* c) {
+  return g_ops[c->layout.scheme][c->prec][c->layout.mapping][c->instr_on ? 1 : 0];
+}
+
+unsigned grid_of(const adept_ctx* c) {
+  if (c->launch.grid) return c->launch.grid;
+  return (unsigned)c->num_cu * (1024u / c->launch.block) * 2u;
+}
+
+adept_status do_reset(adept_ctx* c) {
+  const Plan P = plan(c);
+  KArgs& a = c->args;
+  HIPCHK(hipMemsetAsync(c->arena, 0, P.ctrl + sizeof(Ctrl), c->stream));
+  // the look-back words are cleared in full once here; afterwards every kernel
+  // clears the words of its predecessor
+  HIPCHK(hipMemsetAsync(a.desc[0], 0, P.desc_words * 8, c->stream));
+  HIPCHK(hipMemsetAsync(a.desc[1], 0, P.desc_words * 8, c->stream));
+  HIPCHK(hipMemsetAsync(a.idesc[0], 0, P.idesc_words * 8, c->stream));
+  HIPCHK(hipMemsetAsync(a.idesc[1], 0, P.idesc_words * 8, c->stream));
+  const size_t tally_bytes = P.scratch - P.cont;
+  HIPCHK(hipMemsetAsync((uint8_t*)c->arena + P.cont, 0, tally_bytes, c->stream));
+  HIPCHK(hipMemsetAsync((uint8_t*)c->arena + P.rw, 0, 3 * 2 * 28 * 8, c->stream));
+  for (int t = 0; t < 3; ++t)
+    for (int b = 0; b < 2; ++b)
+      if (a.heat[t][b]) HIPCHK(hipMemsetAsync(a.heat[t][b], 0, c->buf_bytes, c->stream));
+  hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, c->stream, a);
+  hipLaunchKernelGGL(k_reset, dim3(1024), dim3(256), 0, c->stream, a, 0ull, 0ull, 0ull, 0ull);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->host_staged.clear();
+  c->admission_started = false;
+  c->staged_dirty = false;
+  return ADEPT_OK;
+}
+
+adept_status ensure_ready(adept_ctx* c) {
+  if (c->state == FAILED) return fail(c, ADEPT_E_STATE, "context failed earlier: " + c->err);
+  if (c->state == READY) return ADEPT_OK;
+  const Plan P = plan(c);
+  if (!c->arena) {
+    HIPCHK(hipMalloc(&c->arena, P.total));
+    c->arena_size = P.total;
+    c->own_arena = true;
+  }
+  if (!c->stream) {
+    HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    c->own_stream = true;
+  }
+  fill_args(c);
+  HIPCHK(hipMemcpyAsync((void*)c->args.seeds, c->seeds.data(), c->seeds.size() * 4, hipMemcpyHostToDevice,
+                        c->stream));
+  c->state = READY;
+  return do_reset(c);
+}
+
+adept_status sync_mirror(adept_ctx* c) {
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (c->mirror->error) {
+    c->state = FAILED;
+    if (c->mirror->error == ADEPT_E_DEVICE) {
+      c->err = "look-back wait limit reached at iteration " + std::to_string(c->mirror->error_iter);
+      return ADEPT_E_DEVICE;
+    }
+    c->err = "capacity overflow at iteration " + std::to_string(c->mirror->error_iter);
+    return ADEPT_E_CAPACITY;
+  }
+  return ADEPT_OK;
+}
+
+adept_status grow_staged(adept_ctx* c, unsigned long long n) {
+  if (n > c->staged_cap) {
+    if (c->staged) HIPCHK(hipFree(c->staged));
+    c->staged = nullptr;
+    const unsigned long long cap = std::max<unsigned long long>(n, 1024);
+    HIPCHK(hipMalloc(&c->staged, cap * sizeof(adept_primary)));
+    c->staged_cap = cap;
+    c->args.staged = c->staged;
+    c->graph_valid = false;
+  }
+  return ADEPT_OK;
+}
+
+void launch_inject(adept_ctx* c, const KArgs& a, hipStream_t s) {
+  const Ops& o = ops(c);
+  o.inject(a, grid_of(c), c->launch.block, s);
+  hipLaunchKernelGGL(k_inject_epi, dim3(1), dim3(64), 0, s, a);
+}
+
+void launch_iteration(adept_ctx* c, const KArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,
+                      hipEvent_t e1 = nullptr) {
+  const Ops& o = ops(c);
+  if (c->adm_on) {
+    hipLaunchKernelGGL(k_admit, dim3(1), dim3(64), 0, s, a);
+    launch_inject(c, a, s);
+  }
+  if (e0) (void)hipEventRecord(e0, s);
+  o.step(a, grid_of(c), c->launch.block, s);
+  if (e1) (void)hipEventRecord(e1, s);
+  hipLaunchKernelGGL(k_epilogue, dim3(1), dim3(64), 0, s, a);
+}
+
+// Timed mode: iterations launched one by one with events around every step
+// kernel; the elapsed times are summed at each synchronisation.
+adept_status run_timed(adept_ctx* c, const KArgs& a, unsigned long long n) {
+  while (c->ev.size() < 2 * (size_t)c->launch.graph_iters) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    c->ev.push_back(e);
+  }
+  for (unsigned long long k = 0; k < n; ++k) launch_iteration(c, a, c->stream, c->ev[2 * k], c->ev[2 * k + 1]);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (unsigned long long k = 0; k < n; ++k) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]));
+    c->step_ms += ms;
+    c->step_launches += 1;
+  }
+  return ADEPT_OK;
+}
+
+// Upload the staged primaries and their event groups (admission mode).
+adept_status upload_staged(adept_ctx* c) {
+  if (c->adm_on) c->admission_started = true;
+  if (!c->staged_dirty) return ADEPT_OK;
+  const unsigned long long n = c->host_staged.size();
+  adept_status rc = grow_staged(c, n);
+  if (rc) return rc;
+  std::vector<EventGroup> g;
+  for (unsigned long long i = 0; i < n; ++i) {
+    if (i == 0 || c->host_staged[i].event != c->host_staged[i - 1].event) g.push_back(EventGroup{i, 0, 0.0});
+    g.back().count += 1;
+    if (g.back().count > 3ull * c->C) return fail(c, ADEPT_E_CAPACITY, "an event has more primaries than slots");
+  }
+  if (g.size() > c->groups_cap) {
+    if (c->groups) HIPCHK(hipFree(c->groups));
+    c->groups = nullptr;
+    HIPCHK(hipMalloc(&c->groups, std::max<size_t>(g.size(), 16) * sizeof(EventGroup)));
+    c->groups_cap = std::max<size_t>(g.size(), 16);
+    c->args.groups = c->groups;
+    c->graph_valid = false;
+  }
+  if (n) HIPCHK(hipMemcpyAsync(c->staged, c->host_staged.data(), n * sizeof(adept_primary), hipMemcpyHostToDevice,
+                               c->stream));
+  if (!g.empty()) {
+    HIPCHK(hipMemcpyAsync(c->groups, g.data(), g.size() * sizeof(EventGroup), hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(k_group_energy, dim3((unsigned)((g.size() + 255) / 256)), dim3(256), 0, c->stream, c->groups,
+                       (const adept_primary*)c->staged, (unsigned long long)g.size());
+  }
+  // the group table replaces any earlier one: admission restarts at group 0
+  Ctrl* dc = c->args.ctrl;
+  const unsigned long long zero = 0, ng = g.size();
+  HIPCHK(hipMemcpyAsync(&dc->next_group, &zero, 8, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(&dc->n_groups, &ng, 8, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->staged_dirty = false;
+  return ADEPT_OK;
+}
+
+bool valid_primary(const adept_ctx* c, const adept_primary& q) {
+  if (q.type < 0 || q.type > 2 || q.event >= c->seeds.size()) return false;
+  if (!std::isfinite(q.E) || !(q.E > 0.0) || !std::isfinite(q.numIALeft) || (q.trackId >> 63)) return false;
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(q.pos[k]) || !std::isfinite(q.dir[k])) return false;
+  return q.pos[2] >= 0.0 && q.pos[2] < 400.0 && std::fabs(q.pos[0]) <= 200.0 && std::fabs(q.pos[1]) <= 200.0;
+}
+
+// Inject n primaries already copied to c->staged[0..n).
+adept_status inject_staged(adept_ctx* c, unsigned long long n) {
+  hipLaunchKernelGGL(k_set_range, dim3(1), dim3(64), 0, c->stream, c->args, 0ull, n);
+  launch_inject(c, c->args, c->stream);
+  HIPCHK(hipGetLastError());
+  c->graph_valid = c->graph_valid;  // the graph does not reference the range
+  return sync_mirror(c);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+adept_status adept_create(adept_layout layout, adept_precision precision, uint64_t capacity, adept_ctx** out) {
+  if (!out) return ADEPT_E_INVALID;
+  if (layout.scheme < 0 || layout.scheme > 1 || layout.mapping < 0 || layout.mapping > 2) return ADEPT_E_INVALID;
+  if (precision != ADEPT_FP64 && precision != ADEPT_MIXED) return ADEPT_E_INVALID;
+  if (capacity == 0 || capacity > (1ull << 30)) return ADEPT_E_INVALID;
+  if (layout.mapping == ADEPT_MAP_AOSOA) {
+    const uint32_t N = layout.aosoa_lanes;
+    if (N < 2 || N > 256 || (N & (N - 1)) || capacity % N) return ADEPT_E_INVALID;
+  } else {
+    layout.aosoa_lanes = 1;
+  }
+  init_ops();
+  adept_ctx* c = new adept_ctx();
+  c->layout = layout;
+  c->prec = precision;
+  c->C = capacity;
+  if (hipGetDevice(&c->device) != hipSuccess ||
+      hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
+      hipHostMalloc((void**)&c->mirror, sizeof(HostMirror), hipHostMallocMapped) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipMalloc(&c->dev_bad, 8) != hipSuccess) {
+    adept_destroy(c);
+    return ADEPT_E_DEVICE;
+  }
+  memset(c->mirror, 0, sizeof(HostMirror));
+  *out = c;
+  return ADEPT_OK;
+}
+
+adept_status adept_arena_bytes(const adept_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return ADEPT_E_INVALID;
+  *bytes = plan(c).total;
+  return ADEPT_OK;
+}
+
+adept_status adept_bind(adept_ctx* c, void* dev_arena, size_t bytes, void* hip_stream) {
+  if (!c || !dev_arena) return ADEPT_E_INVALID;
+  if (c->state != CREATED || c->arena) return fail(c, ADEPT_E_STATE, "bind after the arena was set up");
+  if (((uintptr_t)dev_arena & 255u) != 0) return fail(c, ADEPT_E_INVALID, "arena must be 256-byte aligned");
+  if (bytes < plan(c).total) return fail(c, ADEPT_E_NOMEM, "arena smaller than adept_arena_bytes");
+  c->arena = dev_arena;
+  c->arena_size = bytes;
+  c->own_arena = false;
+  c->stream = (hipStream_t)hip_stream;
+  if (!c->stream) {
+    // work on the null stream is enqueued on a private blocking stream instead
+    if (hipStreamCreate(&c->stream) != hipSuccess) return fail(c, ADEPT_E_DEVICE, "hipStreamCreate");
+    c->own_stream = true;
+  }
+  return ensure_ready(c);
+}
+
+adept_status adept_set_events(adept_ctx* c, uint32_t n_events, const uint32_t* seeds) {
+  if (!c || n_events == 0 || !seeds) return ADEPT_E_INVALID;
+  if (c->state != CREATED) return fail(c, ADEPT_E_STATE, "set_events after bind");
+  c->seeds.assign(seeds, seeds + n_events);
+  return ADEPT_OK;
+}
+
+adept_status adept_set_scoring(adept_ctx* c, uint32_t nx, uint32_t ny, double pitch_mm) {
+  if (!c || nx == 0 || ny == 0 || !(pitch_mm > 0.0)) return ADEPT_E_INVALID;
+  if (c->state != CREATED) return fail(c, ADEPT_E_STATE, "set_scoring after bind");
+  c->nx = nx;
+  c->ny = ny;
+  c->pitch = pitch_mm;
+  return ADEPT_OK;
+}
+
+adept_status adept_set_admission(adept_ctx* c, int on, double alpha, const double kappa[3]) {
+  if (!c || (on && (!kappa || !(alpha > 0.0)))) return ADEPT_E_INVALID;
+  if (c->state != CREATED) return fail(c, ADEPT_E_STATE, "set_admission after bind");
+  c->adm_on = on ? 1 : 0;
+  c->alpha = alpha;
+  for (int d = 0; d < 3; ++d) c->kappa[d] = kappa ? kappa[d] : 0.0;
+  return ADEPT_OK;
+}
+
+adept_status adept_set_instrumented(adept_ctx* c, int on, uint64_t last_iter) {
+  if (!c) return ADEPT_E_INVALID;
+  if (c->state != CREATED) return fail(c, ADEPT_E_STATE, "set_instrumented after bind");
+  c->instr_on = on ? 1 : 0;
+  c->instr_last = last_iter;
+  return ADEPT_OK;
+}
+
+adept_status adept_set_launch(adept_ctx* c, const adept_launch* l) {
+  if (!c || !l) return ADEPT_E_INVALID;
+  if (l->block != 64 && l->block != 128 && l->block != 256) return fail(c, ADEPT_E_INVALID, "block must be 64, 128 or 256");
+  if (l->graph_iters < 1 || l->graph_iters > 256) return fail(c, ADEPT_E_INVALID, "graph_iters in [1, 256]");
+  c->launch = *l;
+  c->graph_valid = false;
+  return ADEPT_OK;
+}
+
+adept_status adept_get_launch(const adept_ctx* c, adept_launch* l) {
+  if (!c || !l) return ADEPT_E_INVALID;
+  *l = c->launch;
+  l->grid = grid_of(c);
+  return ADEPT_OK;
+}
+
+adept_status adept_inject(adept_ctx* c, const adept_primary* p, uint64_t n) {
+  if (!c || (!p && n)) return ADEPT_E_INVALID;
+  adept_status rc = ensure_ready(c);
+  if (rc) return rc;
+  for (uint64_t i = 0; i < n; ++i)
+    if (!valid_primary(c, p[i])) return fail(c, ADEPT_E_INVALID, "invalid primary at index " + std::to_string(i));
+  if (c->adm_on) {
+    if (c->admission_started) return fail(c, ADEPT_E_STATE, "primaries must be staged before the first iteration");
+    for (uint64_t i = 0; i < n; ++i) {
+      const uint32_t prev = i ? p[i - 1].event : (c->host_staged.empty() ? 0u : c->host_staged.back().event);
+      if (p[i].event < prev) return fail(c, ADEPT_E_INVALID, "admission needs primaries grouped by event");
+    }
+    c->host_staged.insert(c->host_staged.end(), p, p + n);
+    c->staged_dirty = true;
+    return ADEPT_OK;
+  }
+  if (n == 0) return ADEPT_OK;
+  if (n > 3ull * c->C) return fail(c, ADEPT_E_CAPACITY, "more primaries than buffer slots");
+  rc = grow_staged(c, n);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(c->staged, p, n * sizeof(adept_primary), hipMemcpyHostToDevice, c->stream));
+  return inject_staged(c, n);
+}
+
+// Primaries already in device memory (the caller's); checked on the device.
+adept_status adept_inject_device(adept_ctx* c, const adept_primary* dev_p, uint64_t n) {
+  if (!c || (!dev_p && n)) return ADEPT_E_INVALID;
+  adept_status rc = ensure_ready(c);
+  if (rc) return rc;
+  if (c->adm_on) return fail(c, ADEPT_E_UNSUPPORTED, "device injection with admission");
+  if (n == 0) return ADEPT_OK;
+  if (n > 3ull * c->C) return fail(c, ADEPT_E_CAPACITY, "more primaries than buffer slots");
+  rc = grow_staged(c, n);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(c->staged, dev_p, n * sizeof(adept_primary), hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemsetAsync(c->dev_bad, 0, 8, c->stream));
+  hipLaunchKernelGGL(k_validate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, c->args,
+                     (const adept_primary*)c->staged, (unsigned long long)n, c->dev_bad);
+  unsigned long long bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, c->dev_bad, 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (bad) return fail(c, ADEPT_E_INVALID, std::to_string(bad) + " invalid primaries");
+  return inject_staged(c, n);
+}
+
+adept_status adept_step(adept_ctx* c, uint64_t next_counts[3]) {
+  if (!c) return ADEPT_E_INVALID;
+  adept_status rc = ensure_ready(c);
+  if (rc) return rc;
+  rc = upload_staged(c);
+  if (rc) return rc;
+  KArgs a = c->args;
+  a.count_empty = 1;
+  launch_iteration(c, a, c->stream);
+  HIPCHK(hipGetLastError());
+  rc = sync_mirror(c);
+  if (rc) return rc;
+  if (next_counts)
+    for (int d = 0; d < 3; ++d) next_counts[d] = c->mirror->n[d];
+  return ADEPT_OK;
+}
+
+adept_status adept_run(adept_ctx* c, uint64_t max_iter, uint64_t* iters_done) {
+  if (!c) return ADEPT_E_INVALID;
+  adept_status rc = ensure_ready(c);
+  if (rc) return rc;
+  rc = upload_staged(c);
+  if (rc) return rc;
+  KArgs a = c->args;
+  a.count_empty = 0;
+  const unsigned K = c->launch.graph_iters;
+  if (!c->graph_valid || c->graph_k != K) {
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (unsigned k = 0; k < K; ++k) launch_iteration(c, a, c->cap_stream);
+    HIPCHK(hipStreamEndCapture(c->cap_stream, &g));
+    HIPCHK(hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(g);
+    c->graph_valid = true;
+    c->graph_k = K;
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const unsigned long long it0 = c->mirror->iter;
+  c->mirror->done = 0;
+  for (;;) {
+    const unsigned long long done_it = c->mirror->iter - it0;
+    if (done_it >= max_iter) break;
+    if (c->timing) {
+      const unsigned long long n = std::min<unsigned long long>(K, max_iter - done_it);
+      rc = run_timed(c, a, n);
+      if (rc) break;
+    } else if (max_iter - done_it >= K) {
+      HIPCHK(hipGraphLaunch(c->graph, c->stream));
+    } else {
+      for (unsigned long long k = 0; k < max_iter - done_it; ++k) launch_iteration(c, a, c->stream);
+      HIPCHK(hipGetLastError());
+    }
+    rc = sync_mirror(c);
+    if (rc) break;
+    if (c->mirror->done) break;
+  }
+  if (iters_done) *iters_done = c->mirror->iter - it0;
+  return rc;
+}
+
+adept_status adept_tally(adept_ctx* c, adept_tally_kind kind, double* out, size_t n) {
+  if (!c || !out) return ADEPT_E_INVALID;
+  if (c->state != READY && !(c->state == FAILED && c->arena)) return fail(c, ADEPT_E_STATE, "no state yet");
+  const size_t E = c->seeds.size();
+  const KArgs& a = c->args;
+  const double* src = nullptr;
+  size_t want = 0;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  switch (kind) {
+    case ADEPT_T_DEP_CONT: src = a.cont; want = E * kNumVol; break;
+    case ADEPT_T_DEP_CUT: src = a.cut; want = E * kNumVol; break;
+    case ADEPT_T_ESCAPED: src = a.esc; want = E; break;
+    case ADEPT_T_ROUND: src = a.rnd; want = E; break;
+    case ADEPT_T_EIN: src = a.ein; want = E; break;
+    case ADEPT_T_CELLS:
+      if (!a.cells) return fail(c, ADEPT_E_INVALID, "scoring is off");
+      src = a.cells;
+      want = (size_t)kNumLayer * c->nx * c->ny;
+      break;
+    case ADEPT_T_LAYER:
+      want = E * kNumLayer;
+      hipLaunchKernelGGL(k_layer, dim3((unsigned)((want + 255) / 256)), dim3(256), 0, c->stream, a, c->scratch);
+      src = c->scratch;
+      break;
+    case ADEPT_T_INFLIGHT:
+      want = E;
+      HIPCHK(hipMemsetAsync(c->scratch, 0, E * 8, c->stream));
+      ops(c).inflight(a, c->scratch, c->stream);
+      src = c->scratch;
+      break;
+    default:
+      return fail(c, ADEPT_E_INVALID, "unknown tally kind");
+  }
+  if (n != want) return fail(c, ADEPT_E_INVALID, "tally size mismatch: want " + std::to_string(want));
+  HIPCHK(hipMemcpyAsync(out, src, want * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return ADEPT_OK;
+}
+
+adept_status adept_buffer_bytes(const adept_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return ADEPT_E_INVALID;
+  *bytes = buf_bytes_of(c);
+  return ADEPT_OK;
+}
+
+adept_status adept_access_counts(adept_ctx* c, adept_particle t, uint32_t buffer, uint64_t reads[14],
+                                 uint64_t writes[14], uint32_t* heat_words, size_t n_words) {
+  if (!c || t < 0 || t > 2 || buffer > 1) return ADEPT_E_INVALID;
+  if (buffer == 1 && c->layout.scheme != ADEPT_DENSE_DOUBLE) return fail(c, ADEPT_E_INVALID, "sparse has one buffer");
+  if (c->state == CREATED) return fail(c, ADEPT_E_STATE, "no state yet");
+  const KArgs& a = c->args;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  unsigned long long rw[28];
+  HIPCHK(hipMemcpy(rw, a.rw[t][buffer], sizeof(rw), hipMemcpyDeviceToHost));
+  for (int l = 0; l < 14; ++l) {
+    if (reads) reads[l] = rw[2 * l];
+    if (writes) writes[l] = rw[2 * l + 1];
+  }
+  if (heat_words) {
+    if (n_words * 4 != c->buf_bytes) return fail(c, ADEPT_E_INVALID, "n_words must be buffer bytes / 4");
+    if (!a.heat[t][buffer]) {
+      memset(heat_words, 0, n_words * 4);
+    } else {
+      HIPCHK(hipMemcpy(heat_words, a.heat[t][buffer], n_words * 4, hipMemcpyDeviceToHost));
+    }
+  }
+  return ADEPT_OK;
+}
+
+adept_status adept_stats_get(adept_ctx* c, adept_stats* out) {
+  if (!c || !out) return ADEPT_E_INVALID;
+  memset(out, 0, sizeof(*out));
+  if (c->state == CREATED) return ADEPT_OK;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  Ctrl h;
+  HIPCHK(hipMemcpy(&h, c->args.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+  out->iterations = h.iter;
+  for (int d = 0; d < 3; ++d) {
+    out->track_steps[d] = h.steps[d];
+    out->counts[d] = h.n[h.parity][d];
+    out->peak[d] = h.peak[d] > out->counts[d] ? h.peak[d] : out->counts[d];
+  }
+  for (int d = 0; d < 3; ++d) {
+    out->survivors[d] = h.surv[d];
+    out->outputs[d] = h.outputs[d];
+  }
+  out->step_kernel_ms = c->step_ms;
+  out->step_launches = c->step_launches;
+  out->error_iter = h.error_iter;
+  out->waves = h.waves;
+  out->waves_divergent = h.waves_div;
+  out->status = h.error;
+  return ADEPT_OK;
+}
+
+adept_status adept_dump_tracks(adept_ctx* c, adept_particle t, adept_track_host* out, uint32_t* slots, uint64_t cap,
+                               uint64_t* n) {
+  if (!c || t < 0 || t > 2 || !n) return ADEPT_E_INVALID;
+  if (c->state == CREATED) {
+    *n = 0;
+    return ADEPT_OK;
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  Ctrl h;
+  HIPCHK(hipMemcpy(&h, c->args.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+  const unsigned long long cnt = h.n[h.parity][t];
+  if (cap < cnt || (!out && cnt)) {
+    *n = cnt;
+    return fail(c, ADEPT_E_INVALID, "dump buffer too small: need " + std::to_string(cnt));
+  }
+  if (cnt) {
+    adept_track_host* d_out = nullptr;
+    uint32_t* d_slots = nullptr;
+    HIPCHK(hipMalloc(&d_out, cnt * sizeof(adept_track_host)));
+    HIPCHK(hipMalloc(&d_slots, cnt * 4));
+    ops(c).dump(c->args, t, d_out, d_slots, cnt, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(out, d_out, cnt * sizeof(adept_track_host), hipMemcpyDeviceToHost, c->stream));
+    if (slots) HIPCHK(hipMemcpyAsync(slots, d_slots, cnt * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipFree(d_out));
+    HIPCHK(hipFree(d_slots));
+  }
+  *n = cnt;
+  return ADEPT_OK;
+}
+
+adept_status adept_dump_ring(adept_ctx* c, adept_particle t, uint32_t* ring, uint64_t cap, uint64_t* head,
+                             uint64_t* count) {
+  if (!c || t < 0 || t > 2 || !head || !count) return ADEPT_E_INVALID;
+  if (c->layout.scheme != ADEPT_SPARSE_SINGLE) return fail(c, ADEPT_E_INVALID, "no ring in the dense scheme");
+  if (c->state == CREATED) return fail(c, ADEPT_E_STATE, "no state yet");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  Ctrl h;
+  HIPCHK(hipMemcpy(&h, c->args.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+  if (ring) {
+    if (cap < c->C) return fail(c, ADEPT_E_INVALID, "ring buffer too small");
+    HIPCHK(hipMemcpy(ring, c->args.ring[t], c->C * 4, hipMemcpyDeviceToHost));
+  }
+  *head = h.head[t];
+  *count = h.count[t];
+  return ADEPT_OK;
+}
+
+adept_status adept_reset(adept_ctx* c) {
+  if (!c) return ADEPT_E_INVALID;
+  if (c->state == CREATED) return ADEPT_OK;
+  if (!c->arena) return fail(c, ADEPT_E_STATE, "no arena");
+  c->state = READY;
+  c->err.clear();
+  c->step_ms = 0.0;
+  c->step_launches = 0;
+  return do_reset(c);
+}
+
+adept_status adept_autotune(adept_ctx* c, const adept_primary* p, uint64_t n, adept_launch* result) {
+  if (!c || (!p && n)) return ADEPT_E_INVALID;
+  adept_status rc = ensure_ready(c);
+  if (rc) return rc;
+  const adept_launch saved = c->launch;
+  const uint32_t blocks[3] = {64, 128, 256};
+  const uint32_t ks[2] = {16, 64};
+  adept_launch best = saved;
+  float best_ms = 1e30f;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  for (uint32_t b : blocks)
+    for (uint32_t k : ks) {
+      adept_launch l{b, 0, k, 0};
+      adept_set_launch(c, &l);
+      float ms = 0.f;
+      for (int rep = 0; rep < 2; ++rep) {  // the first repetition warms up
+        rc = adept_reset(c);
+        if (!rc) rc = adept_inject(c, p, n);
+        HIPCHK(hipEventRecord(e0, c->stream));
+        uint64_t it = 0;
+        if (!rc) rc = adept_run(c, ~0ull, &it);
+        HIPCHK(hipEventRecord(e1, c->stream));
+        HIPCHK(hipEventSynchronize(e1));
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (rc) break;
+      }
+      if (rc) break;
+      if (ms < best_ms * 0.98f) {  // a smaller block wins unless the larger is 2% faster
+        best_ms = ms;
+        best = l;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) {
+    adept_set_launch(c, &saved);
+    return rc;
+  }
+  adept_set_launch(c, &best);
+  rc = adept_reset(c);
+  if (result) adept_get_launch(c, result);
+  return rc;
+}
+
+adept_status adept_set_timing(adept_ctx* c, int on) {
+  if (!c) return ADEPT_E_INVALID;
+  c->timing = on ? 1 : 0;
+  c->step_ms = 0.0;
+  c->step_launches = 0;
+  return ADEPT_OK;
+}
+
+const char* adept_last_error(const adept_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+void adept_destroy(adept_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  if (c->own_arena && c->arena) (void)hipFree(c->arena);
+  if (c->staged) (void)hipFree(c->staged);
+  if (c->groups) (void)hipFree(c->groups);
+  if (c->dev_bad) (void)hipFree(c->dev_bad);
+  if (c->mirror) (void)hipHostFree(c->mirror);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,778 @@
+// kernels.hpp -- HIP kernels of the transport iteration for gfx950 (wave64).
+//
+// One iteration (paper Sec. 2, both track data structures):
+//   k_step   : a fixed grid of resident blocks takes tiles (one tile = one block
+//              of 64..256 tracks) from an atomic ticket counter; tiles are laid
+//              out electrons | positrons | photons, each in current order.  A
+//              lane loads its track through the record layout, takes one step,
+//              books its deposits in LDS, counts its outputs per particle type;
+//              the block scans the counts with wavefront ballots/shuffles, and
+//              the tile's global offsets come from a single-pass decoupled
+//              look-back (Merrill & Garland 2016) over the tiles before it, so
+//              the next buffers hold the outputs in exactly the canonical order
+//              (every source in order, survivor first, then its creations).
+//   k_epilogue (capi.hip): one wavefront turns the totals into the next counts,
+//              advances the free-slot ring, swaps buffers by flipping the parity.
+// Flags and values of the look-back share one 64-bit word read and written
+// with relaxed device-scope atomics, which bypass the per-XCD L2 caches; no
+// device-scope fences are needed.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/adept.h"
+#include "layout.hpp"
+#include "model.hpp"
+
+namespace adept {
+
+constexpr int kMaxBlock = 256;
+constexpr int kMaxWaves = kMaxBlock / 64;
+
+// Device control block (one per context, in the arena).  Index p = parity
+// selects the current iteration's counts / lists / dense buffers.
+struct Ctrl {
+  unsigned long long n[2][3];       // active counts per parity and type
+  unsigned long long ticket[2];     // tile tickets of the step kernel per parity
+  unsigned long long ntiles[2];     // tiles used by the step kernel of each parity
+  unsigned long long tot[2][9];     // totals published by the last tile of a step
+  unsigned long long head[3], count[3];  // sparse free rings
+  unsigned long long iter;          // iterations done
+  unsigned long long error_iter;
+  unsigned long long steps[3], peak[3];
+  unsigned long long waves, waves_div;
+  unsigned long long surv[3];       // surviving source tracks per type (all iterations)
+  unsigned long long outputs[3];    // tracks written into next buffers per type
+  unsigned long long inj_ticket[2], inj_ntiles[2], inj_tot[3];
+  unsigned long long inj_begin, inj_end;
+  unsigned long long next_group, n_groups;
+  unsigned int parity, inj_parity;
+  int error;
+  unsigned int had_staged;
+  unsigned long long overflow;      // set by kernels that saw an index beyond capacity
+};
+
+// Mirror of the few values the host polls (pinned host memory).
+struct HostMirror {
+  unsigned long long iter;
+  unsigned long long n[3];
+  unsigned long long done;
+  int error;
+  int pad;
+  unsigned long long error_iter;
+};
+
+struct EventGroup {
+  unsigned long long first, count;
+  double energy;
+};
+
+// Everything a kernel needs, by value.
+struct KArgs {
+  Ctrl* ctrl;
+  HostMirror* mirror;
+  uint8_t* buf[3][2];          // dense: current/next by parity; sparse: [t][0]
+  uint32_t* list[3][2];        // sparse slot lists by parity
+  uint32_t* ring[3];           // sparse free rings
+  unsigned long long* desc[2]; // look-back words of the step kernel by parity
+  unsigned long long* idesc[2];// look-back words of the inject kernel by parity
+  double* cont;                // [event][100]
+  double* cut;                 // [event][100]
+  double* esc;                 // [event]
+  double* rnd;                 // [event]
+  double* ein;                 // [event]
+  double* cells;               // [50][nx][ny] or null
+  uint32_t nx, ny;
+  double pitch;
+  const adept_primary* staged; // primaries waiting for injection
+  const EventGroup* groups;
+  const uint32_t* seeds;
+  uint32_t n_events;
+  int scheme;
+  unsigned long long C;
+  MapArgs map;
+  // instrumentation
+  unsigned long long* rw[3][2];
+  uint32_t* heat[3][2];
+  unsigned long long instr_last;
+  int instr_on;
+  // admission
+  int adm_on;
+  double alpha;
+  double kappa[3];
+  // epilogue behaviour: 1 = an iteration with nothing active still counts
+  int count_empty;
+  int pad2;
+};
+
+__device__ __forceinline__ unsigned long long ld_agent(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Ordered compaction: block scan of NV small counts per lane (each < 4, packed
+// as 16-bit fields, four per 64-bit word) and decoupled look-back for the
+// tile's exclusive prefix.  Values are saturated at 2^31 - 1 (capacities are at
+// most 2^30, so a saturated total always reads as an overflow).
+// ---------------------------------------------------------------------------
+constexpr unsigned long long kSat = (1ull << 31) - 1;
+constexpr unsigned long long kStA = 1ull << 62, kStP = 2ull << 62;
+
+template <int NV>
+struct Scan {
+  static constexpr int W = (NV + 3) / 4;
+  unsigned long long wave_tot[kMaxWaves][W];
+  unsigned long long tile_excl[NV];
+  unsigned long long tile_agg[NV];
+  unsigned long long ticket;
+};
+
+__device__ __forceinline__ unsigned long long sat_add(unsigned long long a, unsigned long long b) {
+  const unsigned long long s = a + b;
+  return s > kSat ? kSat : s;
+}
+
+// Block-exclusive prefix per lane (lex) and block aggregate (agg, in LDS).
+template <int NV>
+__device__ __forceinline__ void block_scan(const uint32_t cnt[NV], uint32_t lex[NV], Scan<NV>& sh) {
+  constexpr int W = Scan<NV>::W;
+  const int lane = __lane_id(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  unsigned long long x[W], inc[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    x[w] = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (4 * w + k < NV) x[w] |= (unsigned long long)cnt[4 * w + k] << (16 * k);
+    inc[w] = x[w];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned long long y = __shfl_up(inc[w], o, 64);
+      if (lane >= o) inc[w] += y;
+    }
+    if (lane == 63) sh.wave_tot[wave][w] = inc[w];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    unsigned long long before = 0, all = 0;
+    for (int j = 0; j < nw; ++j) {
+      const unsigned long long t = sh.wave_tot[j][w];
+      if (j < wave) before += t;
+      all += t;
+    }
+    const unsigned long long ex = before + inc[w] - x[w];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (4 * w + k < NV) {
+        lex[4 * w + k] = (uint32_t)((ex >> (16 * k)) & 0xFFFF);
+        if (threadIdx.x == 0) sh.tile_agg[4 * w + k] = (all >> (16 * k)) & 0xFFFF;
+      }
+  }
+  __syncthreads();
+}
+
+// Decoupled look-back by wavefront 0: publishes the tile aggregate, gathers
+// the exclusive prefix from its predecessors, publishes the inclusive prefix.
+// Word layout: [status 2][inclusive 31][aggregate 31].
+// The wait for predecessors is bounded: after kSpinLimit polls the kernel
+// latches an error flag (bit 1 of Ctrl::overflow) and gives up, so every wave
+// always reaches its exit.
+constexpr unsigned kSpinLimit = 1u << 24;
+
+template <int NV>
+__device__ __forceinline__ void lookback(unsigned long long* desc, unsigned long long tile, Scan<NV>& sh,
+                                         unsigned long long* err) {
+  if (threadIdx.x >= 64) return;
+  const int lane = __lane_id();
+  if (tile == 0) {
+    if (lane < NV) {
+      const unsigned long long a = sh.tile_agg[lane];
+      st_agent(&desc[lane], kStP | (a << 31) | a);
+      sh.tile_excl[lane] = 0;
+    }
+    return;
+  }
+  if (lane < NV) st_agent(&desc[tile * NV + lane], kStA | sh.tile_agg[lane]);
+  unsigned long long acc[NV];
+  long long base[NV];
+  bool done[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    acc[v] = 0;
+    base[v] = (long long)tile - 1;
+    done[v] = false;
+  }
+  for (unsigned polls = 0;; ++polls) {
+    if (polls >= kSpinLimit) {
+      if (lane == 0) atomicOr(err, 2ull);
+      break;
+    }
+    bool all_done = true;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      if (done[v]) continue;
+      const long long j = base[v] - lane;
+      const unsigned long long w = j >= 0 ? ld_agent(&desc[(unsigned long long)j * NV + v]) : kStP;
+      const unsigned long long st = w >> 62;
+      const unsigned long long pm = __ballot(st == 2);
+      const unsigned long long xm = __ballot(st == 0);
+      const int fp = pm ? __ffsll((long long)pm) - 1 : 64;
+      const unsigned long long need = fp >= 63 ? ~0ull : ((2ull << fp) - 1);
+      if (xm & need) {
+        all_done = false;
+        continue;  // a tile we depend on has not published yet: read again
+      }
+      unsigned long long val = 0;
+      if (lane < fp) val = w & kSat;                       // aggregates
+      else if (lane == fp) val = (w >> 31) & kSat;         // inclusive prefix
+      const unsigned long long s = wave_sum(val);
+      acc[v] = sat_add(acc[v], s);
+      if (fp < 64) done[v] = true;
+      else {
+        base[v] -= 64;
+        all_done = false;
+      }
+    }
+    if (all_done) break;
+  }
+  if (lane < NV) {
+    unsigned long long ex = 0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      if (v == lane) ex = acc[v];
+    const unsigned long long a = sh.tile_agg[lane];
+    st_agent(&desc[tile * NV + lane], kStP | (sat_add(ex, a) << 31) | a);
+    sh.tile_excl[lane] = ex;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tallies: deposits staged in LDS per block (single-event runs), flushed with
+// device-scope FP64 atomics at the end of the kernel.
+// ---------------------------------------------------------------------------
+struct TallyLDS {
+  double cont[kNumVol];
+  double cut[kNumVol];
+  double esc, rnd;
+};
+
+__device__ __forceinline__ void gadd(double* p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void ladd(double* p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void cell_add(const KArgs& a, int v, double x, double y, double e) {
+  const double hx = (0.5 * (double)a.nx) * a.pitch, hy = (0.5 * (double)a.ny) * a.pitch;
+  const double fx = floor((x + hx) / a.pitch), fy = floor((y + hy) / a.pitch);
+  const uint32_t ix = fx < 0.0 ? 0u : (fx > (double)(a.nx - 1) ? a.nx - 1 : (uint32_t)fx);
+  const uint32_t iy = fy < 0.0 ? 0u : (fy > (double)(a.ny - 1) ? a.ny - 1 : (uint32_t)fy);
+  gadd(&a.cells[((unsigned long long)(v >> 1) * a.nx + ix) * a.ny + iy], e);
+}
+
+// Book one lane's deposits: pre-step volume v, event ev.
+__device__ __forceinline__ void book(const KArgs& a, TallyLDS* tl, uint32_t ev, int v, const Deposits& d,
+                                     const double pos[3]) {
+  if (tl) {
+    if (d.cont != 0.0) ladd(&tl->cont[v], d.cont);
+    if (d.cut != 0.0) ladd(&tl->cut[v], d.cut);
+    if (d.escaped != 0.0) ladd(&tl->esc, d.escaped);
+    if (d.round != 0.0) ladd(&tl->rnd, d.round);
+  } else {
+    if (d.cont != 0.0) gadd(&a.cont[(unsigned long long)ev * kNumVol + v], d.cont);
+    if (d.cut != 0.0) gadd(&a.cut[(unsigned long long)ev * kNumVol + v], d.cut);
+    if (d.escaped != 0.0) gadd(&a.esc[ev], d.escaped);
+    if (d.round != 0.0) gadd(&a.rnd[ev], d.round);
+  }
+  if (a.cells) {
+    if (d.cont != 0.0) cell_add(a, v, d.mid[0], d.mid[1], d.cont);
+    if (d.cut != 0.0) cell_add(a, v, pos[0], pos[1], d.cut);
+  }
+}
+
+__device__ __forceinline__ void flush(const KArgs& a, TallyLDS& tl) {
+  __syncthreads();
+  for (int i = threadIdx.x; i < 2 * kNumVol + 2; i += blockDim.x) {
+    double v;
+    double* dst;
+    if (i < kNumVol) { v = tl.cont[i]; dst = &a.cont[i]; }
+    else if (i < 2 * kNumVol) { v = tl.cut[i - kNumVol]; dst = &a.cut[i - kNumVol]; }
+    else if (i == 2 * kNumVol) { v = tl.esc; dst = a.esc; }
+    else { v = tl.rnd; dst = a.rnd; }
+    if (v != 0.0) gadd(dst, v);
+  }
+}
+
+__device__ __forceinline__ void tally_init(TallyLDS& tl) {
+  for (int i = threadIdx.x; i < kNumVol; i += blockDim.x) {
+    tl.cont[i] = 0.0;
+    tl.cut[i] = 0.0;
+  }
+  if (threadIdx.x == 0) tl.esc = tl.rnd = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Track load / store through the accessor.
+// ---------------------------------------------------------------------------
+template <int MAP, class P, bool INSTR>
+__device__ __forceinline__ void load_track(const Acc<MAP, P::mixed, INSTR>& A, uint64_t s, Track<typename P::R>& t) {
+  using R = typename P::R;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) t.pos[i] = A.template ld<double>(s, i);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) t.dir[i] = A.template ld<R>(s, 3 + i);
+  t.E = A.template ld<R>(s, 6);
+  t.nl = A.template ld<R>(s, 7);
+  t.id = A.template ld<uint64_t>(s, 8);
+  t.seed = A.template ld<uint32_t>(s, 10);
+  t.ctr = A.template ld<uint32_t>(s, 11);
+  t.vol = A.template ld<int32_t>(s, 12);
+  t.event = A.template ld<uint32_t>(s, 13);
+}
+
+template <int MAP, class P, bool INSTR>
+__device__ __forceinline__ void store_full(const Acc<MAP, P::mixed, INSTR>& A, uint64_t s, const double pos[3],
+                                           const typename P::R dir[3], typename P::R E, typename P::R nl, uint64_t id,
+                                           uint64_t parent, uint32_t seed, uint32_t ctr, int32_t vol, uint32_t ev) {
+  using R = typename P::R;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) A.template st<double>(s, i, pos[i]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) A.template st<R>(s, 3 + i, dir[i]);
+  A.template st<R>(s, 6, E);
+  A.template st<R>(s, 7, nl);
+  A.template st<uint64_t>(s, 8, id);
+  A.template st<uint64_t>(s, 9, parent);
+  A.template st<uint32_t>(s, 10, seed);
+  A.template st<uint32_t>(s, 11, ctr);
+  A.template st<int32_t>(s, 12, vol);
+  A.template st<uint32_t>(s, 13, ev);
+}
+
+// Sparse survivor, in place: pos, (dir for e+-), E, numIALeft, rngCtr, volume.
+template <int MAP, class P, bool INSTR>
+__device__ __forceinline__ void store_inplace(const Acc<MAP, P::mixed, INSTR>& A, uint64_t s,
+                                              const Track<typename P::R>& t, bool charged) {
+  using R = typename P::R;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) A.template st<double>(s, i, t.pos[i]);
+  if (charged) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) A.template st<R>(s, 3 + i, t.dir[i]);
+  }
+  A.template st<R>(s, 6, t.E);
+  A.template st<R>(s, 7, t.nl);
+  A.template st<uint32_t>(s, 11, t.ctr);
+  A.template st<int32_t>(s, 12, t.vol);
+}
+
+template <int MAP, class P, bool INSTR>
+__device__ __forceinline__ Acc<MAP, P::mixed, INSTR> make_acc(const KArgs& a, int type, int b, bool on) {
+  Acc<MAP, P::mixed, INSTR> A;
+  A.base = a.buf[type][b];
+  A.m = a.map;
+  A.in.rw = a.rw[type][b];
+  A.in.heat = a.heat[type][b];
+  A.on = on;
+  return A;
+}
+
+__device__ __forceinline__ unsigned long long ceil_div(unsigned long long x, unsigned long long y) {
+  return (x + y - 1) / y;
+}
+
+// Write one creation (full record) of type d at slot s of physical buffer b.
+template <int MAP, class P, bool INSTR>
+__device__ __forceinline__ void write_creation(const KArgs& a, int d, int b, uint64_t s, bool on,
+                                               const Track<typename P::R>& t, const Creations<typename P::R>& cr,
+                                               int i) {
+  using R = typename P::R;
+  const auto A = make_acc<MAP, P, INSTR>(a, d, b, on);
+  R dir[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) dir[k] = cr.dsel[i] == 0 ? t.dir[k] : (cr.dsel[i] == 1 ? cr.d[k] : -cr.d[k]);
+  store_full<MAP, P, INSTR>(A, s, t.pos, dir, cr.E[i], (R)-1, cr.id[i], cr.psel[i] ? cr.vid : t.id, t.seed, 0u,
+                            t.vol, t.event);
+}
+
+// ---------------------------------------------------------------------------
+// The fused step kernel.
+// ---------------------------------------------------------------------------
+template <int SCHEME, int MAP, class P, bool INSTR>
+__global__ void __launch_bounds__(kMaxBlock) k_step(const KArgs a) {
+  using R = typename P::R;
+  constexpr int NV = SCHEME == DENSE ? 3 : 9;  // next[3] (+ new[3], kill[3])
+  __shared__ Scan<NV> sh;
+  __shared__ TallyLDS tl;
+  Ctrl* c = a.ctrl;
+  const uint32_t p = c->parity;
+  const unsigned long long n0 = c->n[p][0], n1 = c->n[p][1], n2 = c->n[p][2];
+  const unsigned long long T = blockDim.x;
+  const unsigned long long t0 = ceil_div(n0, T), t1 = ceil_div(n1, T), t2 = ceil_div(n2, T);
+  const unsigned long long total = t0 + t1 + t2;
+  const bool counting = INSTR && a.instr_on && c->iter < a.instr_last;
+  const bool lds_tally = a.n_events == 1;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    c->ticket[1 - p] = 0;
+    c->ntiles[p] = total;
+  }
+  {  // clear the look-back words of the previous iteration
+    const unsigned long long prev = c->ntiles[1 - p] * NV;
+    unsigned long long* d = a.desc[1 - p];
+    for (unsigned long long i = (unsigned long long)blockIdx.x * T + threadIdx.x; i < prev;
+         i += (unsigned long long)gridDim.x * T)
+      d[i] = 0;
+  }
+  if (blockIdx.x >= total) return;
+  if (lds_tally) tally_init(tl);
+  const int lane = __lane_id();
+  for (;;) {
+    if (threadIdx.x == 0)
+      sh.ticket = __hip_atomic_fetch_add(&c->ticket[p], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const unsigned long long tile = sh.ticket;
+    if (tile >= total) break;
+    int D;
+    unsigned long long lt, nD;
+    if (tile < t0) { D = ELECTRON; lt = tile; nD = n0; }
+    else if (tile < t0 + t1) { D = POSITRON; lt = tile - t0; nD = n1; }
+    else { D = GAMMA; lt = tile - t0 - t1; nD = n2; }
+    const unsigned long long idx = lt * T + threadIdx.x;
+    const bool valid = idx < nD;
+    const int bcur = SCHEME == DENSE ? (int)p : 0;
+    const auto Acur = make_acc<MAP, P, INSTR>(a, D, bcur, counting);
+    uint32_t slot = 0;
+    Track<R> t;
+    Creations<R> cr;
+    cr.n = 0;
+    Deposits dep{0.0, 0.0, 0.0, 0.0, {0.0, 0.0}};
+    bool surv = false;
+    int v0 = 0, lim_code = 0;
+    if (valid) {
+      slot = SCHEME == DENSE ? (uint32_t)idx : a.list[D][p][idx];
+      load_track<MAP, P, INSTR>(Acur, slot, t);
+      v0 = t.vol;
+      surv = D == GAMMA ? step_photon<P>(t, cr, dep) : step_charged<P>(t, D, cr, dep);
+      lim_code = (surv ? 1 : 0) | (cr.n << 1);
+    }
+    {  // divergence diagnostic: lanes of a wavefront that disagree on the outcome
+      const unsigned long long vm = __ballot(valid);
+      if (vm) {
+        const int first = __ffsll((long long)vm) - 1;
+        const int ref = __shfl(lim_code, first, 64);
+        const unsigned long long dm = __ballot(valid && lim_code != ref);
+        const unsigned long long sm = __ballot(valid && surv);
+        if (lane == first) {
+          atomicAdd(&c->waves, 1ull);
+          if (dm) atomicAdd(&c->waves_div, 1ull);
+          if (sm) atomicAdd(&c->surv[D], (unsigned long long)__popcll(sm));
+        }
+      }
+    }
+    // output counts of this lane (constant indices only: the arrays stay in registers)
+    uint32_t cnt[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) cnt[v] = 0;
+    if (valid) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        uint32_t c_new = 0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) c_new += (i < cr.n && cr.type[i] == d) ? 1u : 0u;
+        cnt[d] = c_new + ((surv && D == d) ? 1u : 0u);
+        if (SCHEME == SPARSE) {
+          cnt[3 + d] = c_new;
+          cnt[6 + d] = (!surv && D == d) ? 1u : 0u;
+        }
+      }
+    }
+    uint32_t lex[NV];
+    block_scan<NV>(cnt, lex, sh);
+    lookback<NV>(a.desc[p], tile, sh, &c->overflow);
+    __syncthreads();
+    if (tile == total - 1 && threadIdx.x < NV)
+      c->tot[p][threadIdx.x] = sat_add(sh.tile_excl[threadIdx.x], sh.tile_agg[threadIdx.x]);
+    if (valid) {
+      book(a, lds_tally ? &tl : nullptr, t.event, v0, dep, t.pos);
+      // running position of this lane's next output of each type (next list / dense index)
+      uint32_t k0 = lex[0], k1 = lex[1], k2 = lex[2];
+      auto next_pos = [&](int d) -> unsigned long long {
+        const uint32_t r = d == 0 ? k0++ : (d == 1 ? k1++ : k2++);
+        return sh.tile_excl[d] + r;
+      };
+      if (SCHEME == DENSE) {
+        const int bn = 1 - (int)p;
+        if (surv) {
+          const unsigned long long pos = next_pos(D);
+          const uint64_t parent = Acur.template ld<uint64_t>(slot, 9);
+          if (pos < a.C) {
+            const auto An = make_acc<MAP, P, INSTR>(a, D, bn, counting);
+            store_full<MAP, P, INSTR>(An, pos, t.pos, t.dir, t.E, t.nl, t.id, parent, t.seed, t.ctr, t.vol, t.event);
+          } else {
+            atomicOr(&c->overflow, 1ull);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          if (i < cr.n) {
+            const int d = cr.type[i];
+            const unsigned long long pos = next_pos(d);
+            if (pos < a.C) write_creation<MAP, P, INSTR>(a, d, bn, pos, counting, t, cr, i);
+            else atomicOr(&c->overflow, 1ull);
+          }
+        }
+      } else {
+        uint32_t n0_ = lex[SCHEME == SPARSE ? 3 : 0], n1_ = lex[SCHEME == SPARSE ? 4 : 1],
+                 n2_ = lex[SCHEME == SPARSE ? 5 : 2];
+        if (surv) {
+          const unsigned long long pos = next_pos(D);
+          store_inplace<MAP, P, INSTR>(Acur, slot, t, D != GAMMA);
+          if (pos < a.C) a.list[D][1 - p][pos] = slot;
+        } else {
+          const uint32_t lk = D == 0 ? lex[SCHEME == SPARSE ? 6 : 0]
+                                     : (D == 1 ? lex[SCHEME == SPARSE ? 7 : 0] : lex[SCHEME == SPARSE ? 8 : 0]);
+          const unsigned long long f = sh.tile_excl[6 % NV + (SCHEME == SPARSE ? D : 0)] + lk;
+          a.ring[D][(c->head[D] + c->count[D] + f) % a.C] = slot;
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          if (i < cr.n) {
+            const int d = cr.type[i];
+            const unsigned long long pos = next_pos(d);
+            const uint32_t r = d == 0 ? n0_++ : (d == 1 ? n1_++ : n2_++);
+            const unsigned long long j = sh.tile_excl[(SCHEME == SPARSE ? 3 : 0) + d] + r;
+            if (j < c->count[d] && pos < a.C) {
+              const uint32_t s = a.ring[d][(c->head[d] + j) % a.C];
+              write_creation<MAP, P, INSTR>(a, d, 0, s, counting, t, cr, i);
+              a.list[d][1 - p][pos] = s;
+            } else {
+              atomicOr(&c->overflow, 1ull);
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();  // LDS scan state is reused by the next tile
+  }
+  if (lds_tally) flush(a, tl);
+}
+
+// ---------------------------------------------------------------------------
+// Injection: primaries [inj_begin, inj_end) of the staged array pass through the
+// creation path in input order and are appended after the current tracks.
+// ---------------------------------------------------------------------------
+template <int SCHEME, int MAP, class P, bool INSTR>
+__global__ void __launch_bounds__(kMaxBlock) k_inject(const KArgs a) {
+  using R = typename P::R;
+  constexpr int NV = 3;
+  __shared__ Scan<NV> sh;
+  Ctrl* c = a.ctrl;
+  const uint32_t p = c->parity, q = c->inj_parity;
+  const unsigned long long begin = c->inj_begin, end = c->inj_end;
+  const unsigned long long T = blockDim.x;
+  const unsigned long long total = ceil_div(end - begin, T);
+  const bool counting = INSTR && a.instr_on && c->iter < a.instr_last;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    c->inj_ticket[1 - q] = 0;
+    c->inj_ntiles[q] = total;
+  }
+  {
+    const unsigned long long prev = c->inj_ntiles[1 - q] * NV;
+    unsigned long long* d = a.idesc[1 - q];
+    for (unsigned long long i = (unsigned long long)blockIdx.x * T + threadIdx.x; i < prev;
+         i += (unsigned long long)gridDim.x * T)
+      d[i] = 0;
+  }
+  if (blockIdx.x >= total) return;
+  for (;;) {
+    if (threadIdx.x == 0)
+      sh.ticket = __hip_atomic_fetch_add(&c->inj_ticket[q], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const unsigned long long tile = sh.ticket;
+    if (tile >= total) break;
+    const unsigned long long idx = begin + tile * T + threadIdx.x;
+    const bool valid = idx < end;
+    Track<R> t;
+    Creations<R> cr;
+    cr.n = 0;
+    Deposits dep{0.0, 0.0, 0.0, 0.0, {0.0, 0.0}};
+    int type = 0;
+    bool keep = false;
+    if (valid) {
+      const adept_primary q0 = a.staged[idx];
+      type = q0.type;
+      const uint32_t ev = q0.event;
+      t.pos[0] = q0.pos[0];
+      t.pos[1] = q0.pos[1];
+      t.pos[2] = q0.pos[2];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) t.dir[k] = (R)q0.dir[k];
+      t.E = (R)q0.E;
+      t.nl = (R)q0.numIALeft;
+      t.id = q0.trackId;
+      t.parent = ~0ull;
+      t.seed = a.seeds[ev];
+      t.ctr = 0;
+      t.vol = locate(q0.pos[2]);
+      t.event = ev;
+      gadd(&a.ein[ev], q0.E);
+      if (type == POSITRON) gadd(&a.ein[ev], 2.0 * (double)Consts<R>::me);
+      if (P::mixed) {
+        const double r = q0.E - (double)t.E;
+        if (r != 0.0) gadd(&a.rnd[ev], r);
+      }
+      const bool subcut = type == GAMMA ? (t.E < Consts<R>::cut_g) : (t.E < Consts<R>::cut_e);
+      if (subcut) {
+        dep.cut = (double)t.E;
+        if (type == POSITRON) {
+          const Creator<P> X{t.seed, t.id, 0u, 0};
+          int kidx = 0;
+          annihilate<P>(X, &kidx, 0, cr);
+        }
+        book(a, nullptr, ev, t.vol, dep, t.pos);
+      } else {
+        keep = true;
+      }
+    }
+    uint32_t cnt[NV] = {0, 0, 0};
+    if (valid) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        uint32_t c_ = (keep && type == d) ? 1u : 0u;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) c_ += (i < cr.n && cr.type[i] == d) ? 1u : 0u;
+        cnt[d] = c_;
+      }
+    }
+    uint32_t lex[NV];
+    block_scan<NV>(cnt, lex, sh);
+    lookback<NV>(a.idesc[q], tile, sh, &c->overflow);
+    __syncthreads();
+    if (tile == total - 1 && threadIdx.x < NV)
+      c->inj_tot[threadIdx.x] = sat_add(sh.tile_excl[threadIdx.x], sh.tile_agg[threadIdx.x]);
+    if (valid) {
+      uint32_t k0 = lex[0], k1 = lex[1], k2 = lex[2];
+      const int b = SCHEME == DENSE ? (int)p : 0;
+      const int nout = (keep ? 1 : 0) + cr.n;
+#pragma unroll
+      for (int o = 0; o < 3; ++o) {
+        if (o >= nout) continue;
+        const int d = keep ? type : cr.type[o];
+        const uint32_t r = d == 0 ? k0++ : (d == 1 ? k1++ : k2++);
+        const unsigned long long j = sh.tile_excl[d] + r;
+        unsigned long long s;
+        bool ok;
+        if (SCHEME == DENSE) {
+          s = c->n[p][d] + j;
+          ok = s < a.C;
+        } else {
+          ok = j < c->count[d] && c->n[p][d] + j < a.C;
+          s = ok ? a.ring[d][(c->head[d] + j) % a.C] : 0;
+          if (ok) a.list[d][p][c->n[p][d] + j] = (uint32_t)s;
+        }
+        if (!ok) {
+          atomicOr(&c->overflow, 1ull);
+          continue;
+        }
+        if (keep) {
+          const auto A = make_acc<MAP, P, INSTR>(a, d, b, counting);
+          store_full<MAP, P, INSTR>(A, s, t.pos, t.dir, t.E, t.nl, t.id, ~0ull, t.seed, 0u, t.vol, t.event);
+        } else {
+          write_creation<MAP, P, INSTR>(a, d, b, s, counting, t, cr, o);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Debug / parity: gather the current tracks of one type into host-format records.
+// ---------------------------------------------------------------------------
+template <int SCHEME, int MAP, class P>
+__global__ void k_dump(const KArgs a, int type, adept_track_host* out, uint32_t* slots, unsigned long long n) {
+  const unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t p = a.ctrl->parity;
+  const uint32_t s = SCHEME == DENSE ? (uint32_t)i : a.list[type][p][i];
+  const auto A = make_acc<MAP, P, false>(a, type, SCHEME == DENSE ? (int)p : 0, false);
+  using R = typename P::R;
+  adept_track_host h;
+  for (int k = 0; k < 3; ++k) h.pos[k] = A.template ld<double>(s, k);
+  for (int k = 0; k < 3; ++k) h.dir[k] = (double)A.template ld<R>(s, 3 + k);
+  h.E = (double)A.template ld<R>(s, 6);
+  h.numIALeft = (double)A.template ld<R>(s, 7);
+  h.trackId = A.template ld<uint64_t>(s, 8);
+  h.parentId = A.template ld<uint64_t>(s, 9);
+  h.rngSeed = A.template ld<uint32_t>(s, 10);
+  h.rngCtr = A.template ld<uint32_t>(s, 11);
+  h.volume = A.template ld<int32_t>(s, 12);
+  h.event = A.template ld<uint32_t>(s, 13);
+  out[i] = h;
+  if (slots) slots[i] = s;
+}
+
+// Energy of the buffered tracks per event (+ 2 m_e per positron).
+template <int SCHEME, int MAP, class P>
+__global__ void k_inflight(const KArgs a, double* out) {
+  const uint32_t p = a.ctrl->parity;
+  using R = typename P::R;
+  for (int type = 0; type < 3; ++type) {
+    const unsigned long long n = a.ctrl->n[p][type];
+    const auto A = make_acc<MAP, P, false>(a, type, SCHEME == DENSE ? (int)p : 0, false);
+    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (unsigned long long)gridDim.x * blockDim.x) {
+      const uint32_t s = SCHEME == DENSE ? (uint32_t)i : a.list[type][p][i];
+      const uint32_t ev = A.template ld<uint32_t>(s, 13);
+      gadd(&out[ev], (double)A.template ld<R>(s, 6));
+      if (type == POSITRON) gadd(&out[ev], 2.0 * (double)Consts<R>::me);
+    }
+  }
+}
+
+// Host-side table of the launchers of one (scheme, mapping, precision, instr) variant.
+struct Ops {
+  void (*step)(const KArgs&, unsigned grid, unsigned block, hipStream_t);
+  void (*inject)(const KArgs&, unsigned grid, unsigned block, hipStream_t);
+  void (*dump)(const KArgs&, int type, adept_track_host*, uint32_t*, unsigned long long n, hipStream_t);
+  void (*inflight)(const KArgs&, double*, hipStream_t);
+};
+
+template <int SCHEME, int MAP, class P, bool INSTR>
+struct Variant {
+  static void step(const KArgs& a, unsigned grid, unsigned block, hipStream_t s) {
+    hipLaunchKernelGGL((k_step<SCHEME, MAP, P, INSTR>), dim3(grid), dim3(block), 0, s, a);
+  }
+  static void inject(const KArgs& a, unsigned grid, unsigned block, hipStream_t s) {
+    hipLaunchKernelGGL((k_inject<SCHEME, MAP, P, INSTR>), dim3(grid), dim3(block), 0, s, a);
+  }
+  static void dump(const KArgs& a, int type, adept_track_host* out, uint32_t* slots, unsigned long long n,
+                   hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL((k_dump<SCHEME, MAP, P>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, type, out,
+                       slots, n);
+  }
+  static void inflight(const KArgs& a, double* out, hipStream_t s) {
+    hipLaunchKernelGGL((k_inflight<SCHEME, MAP, P>), dim3(1024), dim3(256), 0, s, a, out);
+  }
+  static Ops ops() { return Ops{&step, &inject, &dump, &inflight}; }
+};
+
+// ops_<scheme>_<precision>(table[map][instr]) are defined one per translation unit.
+void ops_sparse_f64(Ops t[3][2]);
+void ops_sparse_mixed(Ops t[3][2]);
+void ops_dense_f64(Ops t[3][2]);
+void ops_dense_mixed(Ops t[3][2]);
+
+}  // namespace adept

@@ -1,0 +1,246 @@
+"""GPU parity: the HIP library (through its C ABI) against the oracle.
+
+Bit-exact: active counts, slot lists and free rings (sparse), every field of
+every track (FP64 and mixed, -ffp-contract=off on both sides), access counts
+and heatmaps.  Tallies: per-layer deposits within 1e-12 relative (the GPU sums
+in a different order).  Sizes span several tiles and a ragged last tile.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+SCHEMES = [0, 1]
+LAYOUTS = [(0, 1), (1, 1), (2, 64)]  # AoS, SoA, AoSoA-64
+
+
+@pytest.fixture(scope="module")
+def ad():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2302_08252_amd as ad
+
+    ad.lib()
+    return ad
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def compare_state(sim, o, it, scheme, what=""):
+    for t in range(3):
+        g, gs = sim.dump(t)
+        w, ws = o.dump(t)
+        assert len(g) == len(w), (what, it, t, len(g), len(w))
+        if g.tobytes() != w.tobytes():
+            bad = np.nonzero(g.view(np.uint8).reshape(len(g), -1).any(axis=1) !=
+                             w.view(np.uint8).reshape(len(w), -1).any(axis=1))[0]
+            diff = [i for i in range(len(g)) if g[i].tobytes() != w[i].tobytes()][:3]
+            raise AssertionError(f"{what} iter {it} type {t}: first differing tracks {diff}: "
+                                 f"gpu {g[diff[0]]} oracle {w[diff[0]]} ({len(bad)})")
+        if scheme == 0:
+            assert np.array_equal(gs, ws), (what, it, t)
+
+
+def compare_tallies(sim, o, oracle_mod, rtol=1e-12):
+    E = o.n_events
+    gl = sim.tally(oracle_mod.T_LAYER).reshape(E, 50)
+    wl = o.tally(oracle_mod.T_LAYER).reshape(E, 50)
+    assert np.all(np.abs(gl - wl) <= rtol * np.abs(wl) + 1e-300), np.max(np.abs(gl - wl) / np.maximum(np.abs(wl), 1e-300))
+    for k in (oracle_mod.T_ESCAPED, oracle_mod.T_EIN):
+        g, w = sim.tally(k), o.tally(k)
+        assert np.all(np.abs(g - w) <= rtol * np.abs(w) + 1e-300)
+    g, w = sim.tally(oracle_mod.T_ROUND), o.tally(oracle_mod.T_ROUND)
+    assert np.all(np.abs(g - w) <= 1e-12 * o.tally(oracle_mod.T_EIN))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("mapping,lanes", LAYOUTS)
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_iterations_bitwise(ad, oracle_mod, scheme, mapping, lanes, precision):
+    """12 primaries of 300 MeV (several tiles, ragged tails): state after every iteration."""
+    say(f"case iterations_bitwise scheme={scheme} mapping={mapping} lanes={lanes} precision={precision}")
+    C = 1 << 14
+    prims = np.concatenate([workloads.primaries(10, workloads.ELECTRON, 300.0),
+                            workloads.primaries(1, workloads.POSITRON, 40.0, first_id=10),
+                            workloads.primaries(1, workloads.GAMMA, 25.0, first_id=11)])
+    sim = ad.Sim(scheme, mapping, precision, C, lanes, seeds=[3], launch={"block": 64, "graph_iters": 8})
+    o = oracle_mod.Oracle(scheme, precision, C, [3])
+    sim.inject(prims)
+    assert o.inject(prims) == 0
+    compare_state(sim, o, 0, scheme, "inject")
+    it = 0
+    while True:
+        g = sim.step()
+        rc, w = o.step()
+        it += 1
+        assert rc == 0 and list(g) == list(w), (it, g, w)
+        compare_state(sim, o, it, scheme)
+        if scheme == 0:
+            for t in range(3):
+                gr, gh, gc = sim.ring(t)
+                wr, wh, wc = o.ring(t)
+                assert (gh, gc) == (wh, wc) and np.array_equal(gr, wr), (it, t)
+        if w.sum() == 0:
+            break
+    compare_tallies(sim, o, oracle_mod)
+    gs, ws = sim.stats(), o.stats()
+    assert gs["track_steps"] == ws["track_steps"] and gs["iterations"] == ws["iterations"]
+    sim.close()
+
+
+@pytest.mark.parametrize("block", [64, 128, 256])
+def test_cfg0_run_graph(ad, oracle_mod, block):
+    """cfg0 as specified (sparse AoS FP64, 2^20 slots, 100 e- of 1 GeV, seed 1) through
+    adept_run's graph replay: counts and stats exact, per-layer deposits 1e-12."""
+    say(f"case cfg0_run_graph block={block}")
+    wl = workloads.cfg0()
+    sim = ad.Sim(0, 0, 0, 1 << 20, 1, seeds=wl.seeds, launch={"block": block, "graph_iters": 32})
+    sim.inject(wl.primaries)
+    it = sim.run()
+    o, rc, oit = oracle_mod.run_workload(wl, oracle_mod.SPARSE, oracle_mod.FP64, 1 << 20)
+    assert rc == 0 and it == oit
+    gs, ws = sim.stats(), o.stats()
+    assert gs["track_steps"] == ws["track_steps"] and gs["peak"] == ws["peak"]
+    compare_tallies(sim, o, oracle_mod)
+    for t in range(3):
+        gr, gh, gc = sim.ring(t)
+        wr, wh, wc = o.ring(t)
+        assert (gh, gc) == (wh, wc) and np.array_equal(gr, wr)
+    sim.close()
+
+
+def test_single_track_traces(ad, oracle_mod):
+    say("case single_track_traces")
+    for scheme in SCHEMES:
+        for precision in (0, 1):
+            sim = ad.Sim(scheme, 1, precision, 256, 1, seeds=[1], instrumented=1000)
+            o = oracle_mod.Oracle(scheme, precision, 256, [1])
+            o.set_instrumented(True, 1000)
+            p = workloads.primaries(1, workloads.GAMMA, 0.5, num_ia_left=100.0)
+            sim.inject(p)
+            o.inject(p)
+            for it in range(1, 101):
+                assert list(sim.step()) == list(o.step()[1])
+                compare_state(sim, o, it, scheme, "gamma")
+            assert sim.tally(oracle_mod.T_ESCAPED)[0] == 0.5
+            for b in range(2 if scheme else 1):
+                r, w = sim.access_counts(2, b)
+                rr, ww = o.access_totals(2, b)
+                assert np.array_equal(r, rr) and np.array_equal(w, ww)
+            sim.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("mapping,lanes", [(0, 1), (1, 1), (2, 64), (2, 8)])
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_instrumented_counts_and_heatmaps(ad, oracle_mod, scheme, mapping, lanes, precision):
+    """Instrumented mode over injection + the first 20 iterations: per-field read/write
+    totals and per-word heatmaps bit-exact with the oracle's counts expanded through its
+    own byte map of the same layout."""
+    say(f"case instrumented scheme={scheme} mapping={mapping} lanes={lanes} precision={precision}")
+    C = 1 << 12
+    prims = workloads.primaries(4, workloads.ELECTRON, 200.0)
+    sim = ad.Sim(scheme, mapping, precision, C, lanes, seeds=[1], instrumented=20, launch={"block": 128})
+    o = oracle_mod.Oracle(scheme, precision, C, [1])
+    o.set_instrumented(True, 20)
+    sim.inject(prims)
+    o.inject(prims)
+    sim.run(30)
+    o.run(30)
+    for t in range(3):
+        for b in range(2 if scheme else 1):
+            r, w, h = sim.access_counts(t, b, heat=True)
+            rr, ww = o.access_totals(t, b)
+            assert np.array_equal(r, rr) and np.array_equal(w, ww), (t, b, r, rr, w, ww)
+            assert np.array_equal(h, o.heat_words(t, b, mapping, lanes)), (t, b)
+    sim.close()
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_capacity_overflow_iteration(ad, oracle_mod, scheme):
+    say(f"case overflow scheme={scheme}")
+    prims = workloads.primaries(3, workloads.ELECTRON, 1000.0)
+    C = 64
+    o = oracle_mod.Oracle(scheme, 0, C, [1])
+    o.inject(prims)
+    rc, _ = o.run()
+    assert rc == oracle_mod.E_CAPACITY
+    sim = ad.Sim(scheme, 0, 0, C, 1, seeds=[1])
+    sim.inject(prims)
+    with pytest.raises(ad.AdeptError) as e:
+        sim.run()
+    assert e.value.code == ad.E_CAPACITY
+    assert sim.stats()["error_iter"] == o.stats()["error_iter"]
+    sim.close()
+
+
+def test_invalid_primaries_rejected(ad):
+    say("case invalid primaries")
+    sim = ad.Sim(1, 1, 1, 1024, 1, seeds=[1])
+    bad = workloads.primaries(2, workloads.ELECTRON, 10.0)
+    bad["pos"][1, 2] = 401.0
+    with pytest.raises(ad.AdeptError) as e:
+        sim.inject(bad)
+    assert e.value.code == ad.E_INVALID
+    assert list(sim.counts()) == [0, 0, 0]
+    bad = workloads.primaries(1, workloads.ELECTRON, float("nan"))
+    with pytest.raises(ad.AdeptError):
+        sim.inject(bad)
+    bad = workloads.primaries(1, 5, 10.0)
+    with pytest.raises(ad.AdeptError):
+        sim.inject(bad)
+    sim.inject(workloads.primaries(1, workloads.ELECTRON, 10.0))
+    assert sum(sim.counts()) == 1
+    sim.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_admission_and_cells(ad, oracle_mod, precision):
+    """Uneven events of mixed particle types with per-event tallies, admission and
+    per-cell scoring, against the oracle under the same admission rule."""
+    say(f"case batched precision={precision}")
+    wl = workloads.cfg3(n_events=24, max_per_event=6)
+    kappa = [3.0, 2.0, 25.0]
+    C = 1 << 13
+    sim = ad.Sim(1, 1, precision, C, 1, seeds=wl.seeds, scoring=(100, 100, 4.0), admission=(0.8, kappa),
+                 launch={"block": 128, "graph_iters": 16})
+    o = oracle_mod.Oracle(oracle_mod.DENSE, precision, C, wl.seeds)
+    o.set_scoring(100, 100, 4.0)
+    o.set_admission(True, 0.8, kappa)
+    o.stage(wl.primaries)
+    sim.inject(wl.primaries)
+    for it in range(1, 40):
+        g = sim.step()
+        rc, w = o.step()
+        assert rc == 0 and list(g) == list(w), it
+        compare_state(sim, o, it, 1, "batched")
+    rc, oit = o.run()
+    it = sim.run()
+    assert it == oit
+    compare_tallies(sim, o, oracle_mod)
+    gc, wc = sim.tally(oracle_mod.T_CELLS), o.tally(oracle_mod.T_CELLS)
+    assert np.allclose(gc, wc, rtol=1e-12, atol=1e-9)
+    assert sim.stats()["track_steps"] == o.stats()["track_steps"]
+    sim.close()
+
+
+def test_determinism_and_launch_invariance(ad, oracle_mod):
+    say("case determinism")
+    wl = workloads.cfg0().subset(20)
+    res = []
+    for block, k in ((64, 4), (256, 32), (128, 1)):
+        sim = ad.Sim(1, 2, 1, 1 << 16, 32, seeds=wl.seeds, launch={"block": block, "graph_iters": k})
+        sim.inject(wl.primaries)
+        sim.run(25)
+        res.append([sim.dump(t)[0].tobytes() for t in range(3)] + [sim.stats()["track_steps"]])
+        sim.close()
+    assert res[0] == res[1] == res[2]
