@@ -508,7 +508,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(const KArgs a) {
       // running position of this lane's next output of each type (next list / dense index)
       uint32_t k0 = lex[0], k1 = lex[1], k2 = lex[2];
       auto next_pos = [&](int d) -> unsigned long long {
-        const uint32_t r = d == 0 ? k0++ : (d == 1 ? k1++ : k2++);
+        const uint32_t r = d == 0 ? k0 : (d == 1 ? k1 : k2);
+        k0 += d == 0 ? 1u : 0u;
+        k1 += d == 1 ? 1u : 0u;
+        k2 += d == 2 ? 1u : 0u;
         return sh.tile_excl[d] + r;
       };
       if (SCHEME == DENSE) {
@@ -550,7 +553,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(const KArgs a) {
           if (i < cr.n) {
             const int d = cr.type[i];
             const unsigned long long pos = next_pos(d);
-            const uint32_t r = d == 0 ? n0_++ : (d == 1 ? n1_++ : n2_++);
+            const uint32_t r = d == 0 ? n0_ : (d == 1 ? n1_ : n2_);
+            n0_ += d == 0 ? 1u : 0u;
+            n1_ += d == 1 ? 1u : 0u;
+            n2_ += d == 2 ? 1u : 0u;
             const unsigned long long j = sh.tile_excl[(SCHEME == SPARSE ? 3 : 0) + d] + r;
             if (j < c->count[d] && pos < a.C) {
               const uint32_t s = a.ring[d][(c->head[d] + j) % a.C];
@@ -669,7 +675,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_inject(const KArgs a) {
       for (int o = 0; o < 3; ++o) {
         if (o >= nout) continue;
         const int d = keep ? type : cr.type[o];
-        const uint32_t r = d == 0 ? k0++ : (d == 1 ? k1++ : k2++);
+        const uint32_t r = d == 0 ? k0 : (d == 1 ? k1 : k2);
+        k0 += d == 0 ? 1u : 0u;
+        k1 += d == 1 ? 1u : 0u;
+        k2 += d == 2 ? 1u : 0u;
         const unsigned long long j = sh.tile_excl[d] + r;
         unsigned long long s;
         bool ok;

@@ -16,7 +16,7 @@
 //
 // The accessor routes every field load and store through the mapping; its
 // instrumented form (paper Sec. 5) counts reads and writes per field (one
-// atomic per wavefront and access site) and every access per 4-byte word of
+// atomic per wavefront, access site and counter) and every access per 4-byte word of
 // the buffer, indexed by the actual byte address (a per-byte heatmap at 1/4 of
 // the memory, exact because every field is a multiple of 4 bytes).
 #pragma once
@@ -112,11 +112,20 @@ struct Acc {
   Instr in;
   bool on;  // counting window open
 
+  // Lanes of one wavefront may reach the same access site for different buffers
+  // (e.g. creations of different particle types), so the per-field totals are
+  // aggregated per distinct counter: one atomic per counter and site.
   __device__ __forceinline__ void count(uint64_t a, int l, int w) const {
     if (INSTR && on) {
-      const unsigned long long mask = __ballot(1);
-      if ((int)__lane_id() == __ffsll((long long)mask) - 1)
-        atomicAdd(&in.rw[l * 2 + w], (unsigned long long)__popcll(mask));
+      unsigned long long* target = &in.rw[l * 2 + w];
+      unsigned long long pending = __ballot(1);
+      while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const unsigned long long lead_ptr = __shfl((unsigned long long)(uintptr_t)target, leader, 64);
+        const unsigned long long same = __ballot((unsigned long long)(uintptr_t)target == lead_ptr);
+        if ((int)__lane_id() == leader) atomicAdd(target, (unsigned long long)__popcll(same));
+        pending &= ~same;
+      }
       const uint32_t words = Rec<MIXED>::size(l) / 4;
       for (uint32_t k = 0; k < words; ++k) atomicAdd(&in.heat[a / 4 + k], 1u);
     }

@@ -306,9 +306,15 @@ struct Creations {
   // Append one creation; slots are addressed with constant indices only so the
   // arrays stay in registers.
   AD_HD void push(int ty, int ds, int ps, R e, uint64_t i) {
-    if (n == 0) { type[0] = (uint8_t)ty; dsel[0] = (uint8_t)ds; psel[0] = (uint8_t)ps; E[0] = e; id[0] = i; }
-    else if (n == 1) { type[1] = (uint8_t)ty; dsel[1] = (uint8_t)ds; psel[1] = (uint8_t)ps; E[1] = e; id[1] = i; }
-    else { type[2] = (uint8_t)ty; dsel[2] = (uint8_t)ds; psel[2] = (uint8_t)ps; E[2] = e; id[2] = i; }
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {  // value selects, no pointer selects
+      const bool here = n == s;
+      type[s] = here ? (uint8_t)ty : type[s];
+      dsel[s] = here ? (uint8_t)ds : dsel[s];
+      psel[s] = here ? (uint8_t)ps : psel[s];
+      E[s] = here ? e : E[s];
+      id[s] = here ? i : id[s];
+    }
     n += 1;
   }
 };
@@ -395,8 +401,7 @@ AD_HD bool step_charged(Track<typename P::R>& t, int type, Creations<typename P:
   using F = Fmt<R>;
   using C = Consts<R>;
   const uint32_t n = t.ctr;
-  const U4 a = track_block(t.seed, t.id, n, 0u);
-  const U4 b = track_block(t.seed, t.id, n, 1u);
+  const U4 a = track_block(t.seed, t.id, n, 0u);  // block 1 is drawn only where it is used
   const Creator<P> X{t.seed, t.id, n, 0};
   int kidx = 0;
   const int v = t.vol, m = v & 1;
@@ -462,6 +467,7 @@ AD_HD bool step_charged(Track<typename P::R>& t, int type, Creations<typename P:
     const R E2 = E1 - k;
     k = E1 - E2;
     create<P>(X, &kidx, GAMMA, k, out, dep);
+    const U4 b = track_block(t.seed, t.id, n, 1u);
     nl = -plog<R>(P::uni(b.x));
     E = E2;
     if (E2 < C::cut_e) {

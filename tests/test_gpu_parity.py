@@ -244,3 +244,88 @@ def test_determinism_and_launch_invariance(ad, oracle_mod):
         res.append([sim.dump(t)[0].tobytes() for t in range(3)] + [sim.stats()["track_steps"]])
         sim.close()
     assert res[0] == res[1] == res[2]
+
+
+@pytest.mark.parametrize("precision,scheme,mapping", [(1, 1, 1), (0, 0, 0)])
+def test_full_size_one_iteration(ad, oracle_mod, precision, scheme, mapping):
+    """The benchmark workload at full size (10^5 e- of 10 GeV, seed 7, 2^25 slots per
+    type, block 256, 32-iteration graphs): after 60 iterations of graph replay the GPU
+    state (about 10^7 tracks) is handed to the oracle, both take one iteration, and the
+    next states must agree track for track (and slot for slot); the deposits of that
+    iteration agree to 1e-12 of the layer totals."""
+    say(f"case full_size precision={precision} scheme={scheme} mapping={mapping}")
+    wl = workloads.cfg2()
+    C = 1 << 25
+    sim = ad.Sim(scheme, mapping, precision, C, 64, seeds=wl.seeds, launch={"block": 256, "graph_iters": 32})
+    sim.inject(wl.primaries)
+    assert sim.run(60) == 60
+    o = oracle_mod.Oracle(scheme, precision, C, wl.seeds)
+    n_active = 0
+    for t in range(3):
+        tr, slots = sim.dump(t)
+        o.load(t, tr, slots)
+        n_active += len(tr)
+        if scheme == 0:
+            ring, head, count = sim.ring(t)
+            o.set_ring(t, ring, head, count)
+    o.set_iteration(60, dense_current_b=False)
+    assert n_active > 1_000_000
+    before = {k: sim.tally(k) for k in (oracle_mod.T_DEP_CONT, oracle_mod.T_DEP_CUT, oracle_mod.T_ESCAPED)}
+    g = sim.step()
+    rc, w = o.step()
+    assert rc == 0 and list(g) == list(w)
+    compare_state(sim, o, 61, scheme, "full size")
+    for k, b in before.items():
+        inc = sim.tally(k) - b
+        want = o.tally(k)
+        assert np.all(np.abs(inc - want) <= 1e-12 * np.abs(sim.tally(k)).max() + 1e-9), k
+    sim.close()
+
+
+def test_cfg1_layout_study_counts_full_size(ad, oracle_mod):
+    """The layout study at full size: 10^4 e- of 10 GeV (seed 1), instrumented over
+    injection + the first 20 iterations, in sparse AoS and dense AoS / SoA / AoSoA-64
+    (FP64).  Per-field read/write totals and per-word heatmaps bit-exact; the per-field
+    totals are the same for every layout of one scheme."""
+    say("case cfg1 layout study, full size")
+    wl = workloads.cfg1()
+    C = 1 << 22
+    for scheme, layouts in ((0, [(0, 1)]), (1, [(0, 1), (1, 1), (2, 64)])):
+        o = oracle_mod.Oracle(scheme, 0, C, wl.seeds)
+        o.set_instrumented(True, 20)
+        assert o.inject(wl.primaries) == 0
+        rc, _ = o.run(20)
+        assert rc == 0
+        for mapping, lanes in layouts:
+            say(f"  scheme={scheme} mapping={mapping} lanes={lanes}")
+            sim = ad.Sim(scheme, mapping, 0, C, lanes, seeds=wl.seeds, instrumented=20,
+                         launch={"block": 256, "graph_iters": 32})
+            sim.inject(wl.primaries)
+            assert sim.run(20) == 20
+            for t in range(3):
+                for b in range(2 if scheme else 1):
+                    r, w, h = sim.access_counts(t, b, heat=True)
+                    rr, ww = o.access_totals(t, b)
+                    assert np.array_equal(r, rr) and np.array_equal(w, ww), (scheme, mapping, t, b)
+                    assert np.array_equal(h, o.heat_words(t, b, mapping, lanes)), (scheme, mapping, t, b)
+            gs = sim.stats()
+            assert gs["track_steps"] == o.stats()["track_steps"]
+            sim.close()
+
+
+def test_autotune_keeps_results(ad, oracle_mod):
+    """The autotuner only changes the launch configuration: the run it leaves behind
+    reproduces the oracle's counts and deposits."""
+    say("case autotune")
+    wl = workloads.cfg3(n_events=16, max_per_event=20)
+    C = 1 << 16
+    sim = ad.Sim(1, 1, 1, C, 1, seeds=wl.seeds)
+    choice = ad.adept_autotune(sim.ctx, wl.primaries)
+    assert choice["block"] in (64, 128, 256) and choice["graph_iters"] in (16, 64)
+    sim.inject(wl.primaries)
+    sim.run()
+    o, rc, _ = oracle_mod.run_workload(wl, oracle_mod.DENSE, oracle_mod.MIXED, C)
+    assert rc == 0
+    assert sim.stats()["track_steps"] == o.stats()["track_steps"]
+    compare_tallies(sim, o, oracle_mod)
+    sim.close()
