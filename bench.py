@@ -21,6 +21,36 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, AMD's published figure
+KERNEL_SOURCES = ["kernels.hpp", "layout.hpp", "model.hpp", "inst_dense_mixed.hip"]
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_step_cfg2_dense_soa_mixed_pmc.md")
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2302_08252_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per step-kernel launch from the committed rocprofv3 --pmc summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a plain copy of known
+    size), or None if the kernel sources changed since the counters were taken."""
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith("- ") and ":" in line)
+    fields = {k[2:].strip(): v.strip() for k, v in fields.items()}
+    if fields.get("kernel source hash") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["scaled HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -36,6 +66,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=4800, help="primaries of the workload run by the oracle")
     ap.add_argument("--headline-only", action="store_true", help="only the headline path (for profilers)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device to device (a plain copy of known size for scaling counters)")
     return ap.parse_args()
 
 
@@ -148,6 +180,13 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     ad.lib()
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     wl = workloads.cfg2(args.primaries)
     C = 1 << args.capacity_log2
     dev_prims = torch.from_numpy(wl.primaries.view(np.uint8).copy()).cuda()
@@ -185,7 +224,8 @@ def main():
             "bound": "hbm", "kernel": "k_step (fused transport step)",
             "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": (achieved / PEAK_HBM_GBS) if achieved else None,
-            "traffic": None,
+            "traffic": measured_traffic(),
+            "kernel_source_hash": kernel_source_hash(),
             "algorithmic_bytes_per_run": alg,
             "step_launches_timed": st["step_launches"],
             "avg_step_kernel_ms": st["step_kernel_ms"] / max(st["step_launches"], 1),

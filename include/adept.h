@@ -125,7 +125,7 @@ typedef struct {
 
 /* Launch configuration (autotuner output; also settable by hand). */
 typedef struct {
-  uint32_t block;       /* threads per block = compaction tile: 64, 128 or 256   */
+  uint32_t block;       /* threads per block = compaction tile: power of 2, 64-256 */
   uint32_t grid;        /* resident blocks (0: library default)                  */
   uint32_t graph_iters; /* iterations captured per hipGraph replay (1..256)      */
   uint32_t pad;

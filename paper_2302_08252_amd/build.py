@@ -27,19 +27,22 @@ def _newest(paths):
     return max(os.path.getmtime(p) for p in paths)
 
 
-def build(force=True, jobs=None, verbose=False):
+def build(force=True, jobs=None, verbose=False, defines=(), lib_path=LIB, build_dir=BUILD):
     """Compile every HIP translation unit and link libadept.so.  With force=False
-    an up-to-date library is kept."""
-    os.makedirs(BUILD, exist_ok=True)
+    an up-to-date library is kept.  defines: extra -D tuning macros
+    (ADEPT_MAX_BLOCK, ADEPT_WAVES_PER_EU, ADEPT_NT), with lib_path / build_dir for
+    a separate build."""
+    LIB_OUT, BDIR = lib_path, build_dir
+    os.makedirs(BDIR, exist_ok=True)
     hdr = _newest([os.path.join(CSRC, h) for h in HEADERS])
-    if not force and os.path.exists(LIB):
-        if os.path.getmtime(LIB) >= max(hdr, _newest([os.path.join(CSRC, s) for s in SOURCES])):
-            return LIB
+    if not force and os.path.exists(LIB_OUT):
+        if os.path.getmtime(LIB_OUT) >= max(hdr, _newest([os.path.join(CSRC, s) for s in SOURCES])):
+            return LIB_OUT
 
     def compile_one(src):
-        obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-        cmd = ["hipcc", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
-        r = subprocess.run(cmd, capture_output=True, text=True, cwd=BUILD)
+        obj = os.path.join(BDIR, src.replace(".hip", ".o"))
+        cmd = ["hipcc", *FLAGS, *[f"-D{d}" for d in defines], "-c", os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True, cwd=BDIR)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
         if verbose:
@@ -49,13 +52,13 @@ def build(force=True, jobs=None, verbose=False):
     jobs = jobs or min(len(SOURCES), os.cpu_count() or 1)
     with concurrent.futures.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(compile_one, SOURCES))
-    tmp = LIB + ".tmp"
+    tmp = LIB_OUT + ".tmp"
     r = subprocess.run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs],
-                       capture_output=True, text=True, cwd=BUILD)
+                       capture_output=True, text=True, cwd=BDIR)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, LIB_OUT)
+    return LIB_OUT
 
 
 if __name__ == "__main__":

@@ -175,6 +175,24 @@ __global__ void k_group_energy(EventGroup* g, const adept_primary* p, unsigned l
   g[i].energy = e;
 }
 
+// Fold the per-block tally rows (single-event runs) into event 0's tallies, in
+// row order, and clear them.
+__global__ void k_fold_rows(const KArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kRowLen) return;
+  double s = 0.0;
+  for (unsigned r = 0; r < kMaxGrid; ++r) {
+    double* row = a.rows + (unsigned long long)r * kRowLen;
+    s += row[i];
+    row[i] = 0.0;
+  }
+  if (s == 0.0) return;
+  if (i < kNumVol) a.cont[i] += s;
+  else if (i < 2 * kNumVol) a.cut[i - kNumVol] += s;
+  else if (i == 2 * kNumVol) a.esc[0] += s;
+  else a.rnd[0] += s;
+}
+
 __global__ void k_layer(const KArgs a, double* out) {
   const unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (unsigned long long)a.n_events * kNumLayer) return;
@@ -287,7 +305,7 @@ adept_status fail(adept_ctx* c, adept_status code, const std::string& msg) {
   } while (0)
 
 struct Plan {
-  size_t ctrl, buf[3][2], list[3][2], ring[3], desc[2], idesc[2], cont, cut, esc, rnd, ein, cells, scratch, rw,
+  size_t ctrl, buf[3][2], list[3][2], ring[3], desc[2], idesc[2], cont, cut, esc, rnd, ein, cells, rows, scratch, rw,
       heat[3][2], seeds, total;
   unsigned long long desc_words, idesc_words;
 };
@@ -328,6 +346,7 @@ Plan plan(const adept_ctx* c) {
   P.ein = bump(at, E * 8);
   const size_t ncell = (size_t)kNumLayer * c->nx * c->ny;
   P.cells = ncell ? bump(at, ncell * 8) : 0;
+  P.rows = bump(at, (size_t)kMaxGrid * kRowLen * 8);
   P.scratch = bump(at, std::max<size_t>(E * kNumVol, ncell) * 8 + 8);
   P.rw = bump(at, 3 * 2 * 28 * 8);
   for (int t = 0; t < 3; ++t)
@@ -364,6 +383,7 @@ void fill_args(adept_ctx* c) {
   a.rnd = (double*)(A + P.rnd);
   a.ein = (double*)(A + P.ein);
   a.cells = P.cells ? (double*)(A + P.cells) : nullptr;
+  a.rows = (double*)(A + P.rows);
   a.nx = c->nx;
   a.ny = c->ny;
   a.pitch = c->pitch;
@@ -391,7 +411,7 @@ const Ops& ops(const adept_ctx* c) {
 
 unsigned grid_of(const adept_ctx* c) {
   if (c->launch.grid) return c->launch.grid;
-  return (unsigned)c->num_cu * (1024u / c->launch.block) * 2u;
+  return std::min<unsigned>(kMaxGrid, (unsigned)c->num_cu * (1024u / c->launch.block) * 2u);
 }
 
 adept_status do_reset(adept_ctx* c) {
@@ -655,8 +675,10 @@ adept_status adept_set_instrumented(adept_ctx* c, int on, uint64_t last_iter) {
 
 adept_status adept_set_launch(adept_ctx* c, const adept_launch* l) {
   if (!c || !l) return ADEPT_E_INVALID;
-  if (l->block != 64 && l->block != 128 && l->block != 256) return fail(c, ADEPT_E_INVALID, "block must be 64, 128 or 256");
+  if (l->block < 64 || l->block > (uint32_t)kMaxBlock || (l->block & (l->block - 1)))
+    return fail(c, ADEPT_E_INVALID, "block must be a power of two in [64, " + std::to_string(kMaxBlock) + "]");
   if (l->graph_iters < 1 || l->graph_iters > 256) return fail(c, ADEPT_E_INVALID, "graph_iters in [1, 256]");
+  if (l->grid > kMaxGrid) return fail(c, ADEPT_E_INVALID, "grid above the maximum of 8192 blocks");
   c->launch = *l;
   c->graph_valid = false;
   return ADEPT_OK;
@@ -783,6 +805,7 @@ adept_status adept_tally(adept_ctx* c, adept_tally_kind kind, double* out, size_
   const KArgs& a = c->args;
   const double* src = nullptr;
   size_t want = 0;
+  hipLaunchKernelGGL(k_fold_rows, dim3(1), dim3(256), 0, c->stream, a);
   HIPCHK(hipStreamSynchronize(c->stream));
   switch (kind) {
     case ADEPT_T_DEP_CONT: src = a.cont; want = E * kNumVol; break;

@@ -26,8 +26,23 @@
 
 namespace adept {
 
-constexpr int kMaxBlock = 256;
+#ifndef ADEPT_MAX_BLOCK
+#define ADEPT_MAX_BLOCK 256
+#endif
+// Occupancy hint for the step kernel (minimum waves per SIMD; 0: none).
+#ifndef ADEPT_WAVES_PER_EU
+#define ADEPT_WAVES_PER_EU 0
+#endif
+#if ADEPT_WAVES_PER_EU > 0
+#define ADEPT_STEP_ATTR __attribute__((amdgpu_waves_per_eu(ADEPT_WAVES_PER_EU)))
+#else
+#define ADEPT_STEP_ATTR
+#endif
+
+constexpr int kMaxBlock = ADEPT_MAX_BLOCK;
 constexpr int kMaxWaves = kMaxBlock / 64;
+constexpr unsigned kMaxGrid = 8192;          // largest grid of the step kernel
+constexpr int kRowLen = 2 * 100 + 2;         // continuous[100], local[100], escaped, rounding
 
 // Device control block (one per context, in the arena).  Index p = parity
 // selects the current iteration's counts / lists / dense buffers.
@@ -82,6 +97,7 @@ struct KArgs {
   double* rnd;                 // [event]
   double* ein;                 // [event]
   double* cells;               // [50][nx][ny] or null
+  double* rows;                // single-event runs: one tally row per block index, kRowLen doubles
   uint32_t nx, ny;
   double pitch;
   const adept_primary* staged; // primaries waiting for injection
@@ -266,6 +282,11 @@ struct TallyLDS {
   double esc, rnd;
 };
 
+// Per-block statistics, flushed with one atomic per counter at the end.
+struct StatLDS {
+  unsigned long long waves, waves_div, surv[3];
+};
+
 __device__ __forceinline__ void gadd(double* p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -301,16 +322,19 @@ __device__ __forceinline__ void book(const KArgs& a, TallyLDS* tl, uint32_t ev, 
   }
 }
 
+// The block's partial sums go to its own row (plain read-modify-write: no other
+// block writes this row during the launch); rows are folded into the event
+// tallies in a fixed order when the tallies are read.
 __device__ __forceinline__ void flush(const KArgs& a, TallyLDS& tl) {
   __syncthreads();
-  for (int i = threadIdx.x; i < 2 * kNumVol + 2; i += blockDim.x) {
+  double* row = a.rows + (unsigned long long)blockIdx.x * kRowLen;
+  for (int i = threadIdx.x; i < kRowLen; i += blockDim.x) {
     double v;
-    double* dst;
-    if (i < kNumVol) { v = tl.cont[i]; dst = &a.cont[i]; }
-    else if (i < 2 * kNumVol) { v = tl.cut[i - kNumVol]; dst = &a.cut[i - kNumVol]; }
-    else if (i == 2 * kNumVol) { v = tl.esc; dst = a.esc; }
-    else { v = tl.rnd; dst = a.rnd; }
-    if (v != 0.0) gadd(dst, v);
+    if (i < kNumVol) v = tl.cont[i];
+    else if (i < 2 * kNumVol) v = tl.cut[i - kNumVol];
+    else if (i == 2 * kNumVol) v = tl.esc;
+    else v = tl.rnd;
+    if (v != 0.0) row[i] += v;
   }
 }
 
@@ -410,11 +434,12 @@ __device__ __forceinline__ void write_creation(const KArgs& a, int d, int b, uin
 // The fused step kernel.
 // ---------------------------------------------------------------------------
 template <int SCHEME, int MAP, class P, bool INSTR>
-__global__ void __launch_bounds__(kMaxBlock) k_step(const KArgs a) {
+__global__ void __launch_bounds__(kMaxBlock) ADEPT_STEP_ATTR k_step(const KArgs a) {
   using R = typename P::R;
   constexpr int NV = SCHEME == DENSE ? 3 : 9;  // next[3] (+ new[3], kill[3])
   __shared__ Scan<NV> sh;
   __shared__ TallyLDS tl;
+  __shared__ StatLDS ss;
   Ctrl* c = a.ctrl;
   const uint32_t p = c->parity;
   const unsigned long long n0 = c->n[p][0], n1 = c->n[p][1], n2 = c->n[p][2];
@@ -436,13 +461,22 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(const KArgs a) {
   }
   if (blockIdx.x >= total) return;
   if (lds_tally) tally_init(tl);
+  if (threadIdx.x == 0) ss.waves = ss.waves_div = ss.surv[0] = ss.surv[1] = ss.surv[2] = 0;
+  __syncthreads();
   const int lane = __lane_id();
+  // The ticket of the block's next tile is taken while the current tile is
+  // processed, so the atomic's latency overlaps the tile's work.  Holding it
+  // early cannot block anybody: this block reaches that tile next.
+  unsigned long long my_next = 0;  // thread 0: ticket of the following tile, kept in a register
+  if (threadIdx.x == 0)
+    my_next = __hip_atomic_fetch_add(&c->ticket[p], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (;;) {
-    if (threadIdx.x == 0)
-      sh.ticket = __hip_atomic_fetch_add(&c->ticket[p], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) sh.ticket = my_next;
     __syncthreads();
     const unsigned long long tile = sh.ticket;
     if (tile >= total) break;
+    if (threadIdx.x == 0)
+      my_next = __hip_atomic_fetch_add(&c->ticket[p], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int D;
     unsigned long long lt, nD;
     if (tile < t0) { D = ELECTRON; lt = tile; nD = n0; }
@@ -474,9 +508,9 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(const KArgs a) {
         const unsigned long long dm = __ballot(valid && lim_code != ref);
         const unsigned long long sm = __ballot(valid && surv);
         if (lane == first) {
-          atomicAdd(&c->waves, 1ull);
-          if (dm) atomicAdd(&c->waves_div, 1ull);
-          if (sm) atomicAdd(&c->surv[D], (unsigned long long)__popcll(sm));
+          atomicAdd(&ss.waves, 1ull);
+          if (dm) atomicAdd(&ss.waves_div, 1ull);
+          if (sm) atomicAdd(&ss.surv[D], (unsigned long long)__popcll(sm));
         }
       }
     }
@@ -572,6 +606,13 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(const KArgs a) {
     __syncthreads();  // LDS scan state is reused by the next tile
   }
   if (lds_tally) flush(a, tl);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicAdd(&c->waves, ss.waves);
+    if (ss.waves_div) atomicAdd(&c->waves_div, ss.waves_div);
+    for (int d = 0; d < 3; ++d)
+      if (ss.surv[d]) atomicAdd(&c->surv[d], ss.surv[d]);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -23,6 +23,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Streaming (non-temporal) loads and stores of track fields: every field is
+// read once and written once per iteration, far beyond the caches' reach.
+#ifndef ADEPT_NT
+#define ADEPT_NT 0
+#endif
+
 namespace adept {
 
 enum : int { MAP_AOS = 0, MAP_SOA = 1, MAP_AOSOA = 2 };
@@ -134,13 +140,15 @@ struct Acc {
   __device__ __forceinline__ T ld(uint64_t slot, int l) const {
     const uint64_t a = leaf_addr<MAP, MIXED>(m, slot, l);
     count(a, l, 0);
+    if (ADEPT_NT) return __builtin_nontemporal_load(reinterpret_cast<const T*>(base + a));
     return *reinterpret_cast<const T*>(base + a);
   }
   template <class T>
   __device__ __forceinline__ void st(uint64_t slot, int l, T v) const {
     const uint64_t a = leaf_addr<MAP, MIXED>(m, slot, l);
     count(a, l, 1);
-    *reinterpret_cast<T*>(base + a) = v;
+    if (ADEPT_NT) __builtin_nontemporal_store(v, reinterpret_cast<T*>(base + a));
+    else *reinterpret_cast<T*>(base + a) = v;
   }
 };
 

@@ -210,7 +210,7 @@ def test_batched_admission_and_cells(ad, oracle_mod, precision):
     say(f"case batched precision={precision}")
     wl = workloads.cfg3(n_events=24, max_per_event=6)
     kappa = [3.0, 2.0, 25.0]
-    C = 1 << 13
+    C = 1 << 15
     sim = ad.Sim(1, 1, precision, C, 1, seeds=wl.seeds, scoring=(100, 100, 4.0), admission=(0.8, kappa),
                  launch={"block": 128, "graph_iters": 16})
     o = oracle_mod.Oracle(oracle_mod.DENSE, precision, C, wl.seeds)
@@ -224,6 +224,7 @@ def test_batched_admission_and_cells(ad, oracle_mod, precision):
         assert rc == 0 and list(g) == list(w), it
         compare_state(sim, o, it, 1, "batched")
     rc, oit = o.run()
+    assert rc == 0
     it = sim.run()
     assert it == oit
     compare_tallies(sim, o, oracle_mod)
