@@ -66,6 +66,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=4800, help="primaries of the workload run by the oracle")
     ap.add_argument("--headline-only", action="store_true", help="only the headline path (for profilers)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched uneven-events section")
+    ap.add_argument("--per-event-sample", type=int, default=32, help="events timed one launch sequence each")
+    ap.add_argument("--cfg4", action="store_true", help="also run 10^6 e- in 1000 events with 500k cells")
+    ap.add_argument("--layout-study", action="store_true",
+                    help="also time cfg1 in the paper's four layouts and summarise its access counts")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device to device (a plain copy of known size for scaling counters)")
     return ap.parse_args()
@@ -166,6 +171,140 @@ def _oracle_chunk(a):
     return sum(o.stats()["track_steps"])
 
 
+def kappa_cfg1():
+    path = os.path.join(ROOT, "tests", "golden", "kappa_cfg1.txt")
+    line = [l for l in open(path) if not l.startswith("#")][0]
+    return [float(x) for x in line.split()]
+
+
+def run_once(ad, torch, sim, prims=None, dev=None):
+    """Time one run (primaries staged beforehand: admission uploads them at the
+    first call, which max_iter=0 triggers outside the timed region)."""
+    sim.reset()
+    if dev is not None:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ad.adept_inject_device(sim.ctx, dev.data_ptr(), len(prims))
+    else:
+        sim.inject(prims)
+        sim.run(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+    it = sim.run()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, it, sim.stats()
+
+
+def batched_section(ad, torch, np, workloads, args):
+    """512 uneven events (cfg3): layout and launch picked by the autotuner on a
+    16-event sample, events admitted by the capacity rule, per-event tallies."""
+    wl = workloads.cfg3()
+    kappa = kappa_cfg1()
+    C = 1 << 24
+    cands = [(1, 0, 1), (1, 1, 1), (1, 2, 16), (1, 2, 64), (1, 2, 256)]
+    sample = wl.primaries[wl.primaries["event"] < 16]
+    layout, launch, _ = ad.adept_autotune_layout(ad.MIXED, 1 << 21, cands, wl.seeds[:16], sample)
+    out = {"workload": wl.description, "capacity_per_type": C, "admission": {"alpha": 0.8, "kappa_per_GeV": kappa},
+           "autotuned": {"layout": {"scheme": "dense" if layout[0] else "sparse",
+                                    "mapping": ["AoS", "SoA", "AoSoA"][layout[1]], "lanes": layout[2]},
+                         "launch": launch, "tuning_sample": "events 0-15"}}
+    sim = ad.Sim(layout[0], layout[1], ad.MIXED, C, layout[2], seeds=wl.seeds, admission=(0.8, kappa), launch=launch)
+    dt, it, st = run_once(ad, torch, sim, wl.primaries)
+    ts = sum(st["track_steps"])
+    lay_m = sim.tally(ad.T_LAYER).reshape(len(wl.seeds), 50).sum(axis=0)
+    sim.close()
+    out["mixed"] = {"seconds": dt, "track_steps": ts, "track_steps_per_s": ts / dt, "iterations": it,
+                    "primaries_per_s": len(wl.primaries) / dt, "divergent_wave_fraction": st["waves_divergent"] / max(st["waves"], 1)}
+    # the FP64 sparse single buffer (the paper's baseline structure), same admission
+    sp = ad.Sim(0, 0, ad.FP64, C, 1, seeds=wl.seeds, admission=(0.8, kappa), launch=launch)
+    dt2, it2, st2 = run_once(ad, torch, sp, wl.primaries)
+    lay_f = sp.tally(ad.T_LAYER).reshape(len(wl.seeds), 50).sum(axis=0)
+    sp.close()
+    ts2 = sum(st2["track_steps"])
+    out["fp64_sparse_aos"] = {"seconds": dt2, "track_steps_per_s": ts2 / dt2}
+    out["speedup_vs_fp64_sparse_aos"] = dt2 / dt
+    rel = np.abs(lay_m - lay_f) / lay_f
+    out["edep_per_layer_rel_error_mixed_vs_fp64"] = {"max": float(rel.max()),
+                                                     "total": float(abs(lay_m.sum() - lay_f.sum()) / lay_f.sum())}
+    # one launch sequence per event, on a sample of events
+    k = args.per_event_sample
+    pe = ad.Sim(layout[0], layout[1], ad.MIXED, C, layout[2], seeds=wl.seeds, launch=launch)
+    tot_t = tot_s = 0.0
+    for e in range(k):
+        d, _, s = run_once(ad, torch, pe, wl.primaries[wl.primaries["event"] == e])
+        tot_t += d
+        tot_s += sum(s["track_steps"])
+    pe.close()
+    out["one_launch_sequence_per_event"] = {"events_sampled": k, "track_steps_per_s": tot_s / tot_t}
+    out["batched_speedup_vs_per_event"] = (ts / dt) / (tot_s / tot_t)
+    return out
+
+
+def cfg4_section(ad, torch, np, workloads):
+    wl = workloads.cfg4()
+    C = 1 << 28
+    kappa = kappa_cfg1()
+    sim = ad.Sim(ad.DENSE_DOUBLE, ad.MAP_SOA, ad.MIXED, C, 64, seeds=wl.seeds, scoring=(100, 100, 4.0),
+                 admission=(0.8, kappa), launch={"block": 256, "graph_iters": 32})
+    ad.adept_set_timing(sim.ctx, True)
+    dt, it, st = run_once(ad, torch, sim, wl.primaries)
+    cells = sim.tally(ad.T_CELLS)
+    lay = sim.tally(ad.T_LAYER).reshape(len(wl.seeds), 50).sum(axis=0)
+    sim.close()
+    alg = algorithmic_bytes(st, 1, 1)
+    ts = sum(st["track_steps"])
+    return {"workload": wl.description + ", 100x100 cells of 4 mm per layer", "capacity_per_type": C,
+            "seconds": dt, "track_steps_per_s": ts / dt, "iterations": it,
+            "step_kernel_GBps": alg / (st["step_kernel_ms"] / 1e3) / 1e9,
+            "frac_of_hbm_peak": alg / (st["step_kernel_ms"] / 1e3) / 1e9 / PEAK_HBM_GBS,
+            "divergent_wave_fraction": st["waves_divergent"] / max(st["waves"], 1),
+            "cells_sum_over_layer_sum": float(cells.sum() / lay.sum())}
+
+
+def layout_study(ad, torch, np, workloads):
+    """Paper Sec. 4-5 on the toy model: 10^4 e- of 10 GeV (FP64) timed in the sparse
+    single buffer (AoS) and the dense double buffer (AoS, SoA, AoSoA-64); then, in
+    instrumented mode over injection + 20 iterations, the per-field access counts of
+    the electron buffer, slot utilisation and the per-type maximum access counts."""
+    wl = workloads.cfg1()
+    C = 1 << 22
+    dev = torch.from_numpy(wl.primaries.view(np.uint8).copy()).cuda()
+    res = {"workload": wl.description, "precision": "FP64", "timings": {}}
+    for name, (s, m, n) in {"sparse AoS": (0, 0, 1), "dense AoS": (1, 0, 1), "dense SoA": (1, 1, 1),
+                            "dense AoSoA-64": (1, 2, 64)}.items():
+        sim = ad.Sim(s, m, ad.FP64, C, n, seeds=wl.seeds, launch={"block": 256, "graph_iters": 32})
+        best = 1e9
+        for r in range(3):
+            dt, it, st = run_once(ad, torch, sim, wl.primaries, dev)
+            if r:
+                best = min(best, dt)
+        sim.close()
+        res["timings"][name] = {"ms": best * 1e3, "track_steps_per_s": sum(st["track_steps"]) / best}
+    counts = {}
+    for name, (s, m, n) in {"sparse AoS": (0, 0, 1), "dense AoS": (1, 0, 1)}.items():
+        sim = ad.Sim(s, m, ad.FP64, C, n, seeds=wl.seeds, instrumented=20)
+        sim.inject(wl.primaries)
+        sim.run(20)
+        rec = {}
+        for t, tn in enumerate(("electrons", "positrons", "photons")):
+            hs = [sim.access_counts(t, b, heat=True) for b in range(2 if s else 1)]
+            heat = np.concatenate([h[2] for h in hs])
+            per_slot = heat.reshape(-1, 24).sum(axis=1)  # 96-byte records = 24 words
+            rec[tn] = {"reads_per_field": [int(x) for x in sum(h[0] for h in hs)],
+                       "writes_per_field": [int(x) for x in sum(h[1] for h in hs)],
+                       "max_word_count": int(heat.max()), "slots_touched": int(np.count_nonzero(per_slot))}
+        sim.close()
+        counts[name] = rec
+    res["instrumented_first_20_iterations"] = counts
+    sp, dn = counts["sparse AoS"], counts["dense AoS"]
+    res["paper_claims"] = {
+        "slots_touched_sparse_vs_dense_electrons": [sp["electrons"]["slots_touched"], dn["electrons"]["slots_touched"]],
+        "max_access_ratio_e-/e+_sparse": sp["electrons"]["max_word_count"] / max(sp["positrons"]["max_word_count"], 1),
+        "max_access_ratio_e-/gamma_sparse": sp["electrons"]["max_word_count"] / max(sp["photons"]["max_word_count"], 1),
+    }
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -249,6 +388,12 @@ def main():
             "total": float(abs(lm.sum() - lf.sum()) / lf.sum()),
             "reference": "the same workload in FP64 on the GPU (bit-exact with the FP64 oracle per track)",
         }
+    if not args.headline_only and not args.no_batched:
+        out["batched_cfg3"] = batched_section(ad, torch, np, workloads, args)
+    if args.cfg4:
+        out["cfg4"] = cfg4_section(ad, torch, np, workloads)
+    if args.layout_study:
+        out["layout_study_cfg1"] = layout_study(ad, torch, np, workloads)
     if not args.headline_only and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample, 1)
     print(json.dumps(out), flush=True)

@@ -219,7 +219,7 @@ adept_status adept_dump_ring(adept_ctx* ctx, adept_particle t, uint32_t* ring, u
 adept_status adept_reset(adept_ctx* ctx);
 
 /* Pick the launch configuration (block size = compaction tile, grid, graph
- * iterations) for this context by timing short runs of the given primaries on
+ * iterations) for this context by timing runs of the given primaries on
  * scratch state; the context is reset afterwards.  Ties go to the smaller
  * block.  result (nullable) receives the choice. */
 adept_status adept_autotune(adept_ctx* ctx, const adept_primary* p, uint64_t n, adept_launch* result);
@@ -228,6 +228,16 @@ adept_status adept_autotune(adept_ctx* ctx, const adept_primary* p, uint64_t n, 
  * HIP events around every step kernel and accumulates their durations into
  * adept_stats (step_kernel_ms, step_launches); resets the accumulators. */
 adept_status adept_set_timing(adept_ctx* ctx, int on);
+
+/* Layout autotuner: for every candidate layout, a scratch context (library-
+ * owned memory, the given precision, capacity and event seeds) is tuned with
+ * adept_autotune on the given primaries and the tuned configuration is timed on
+ * one more run; the fastest layout wins (an earlier candidate wins unless a
+ * later one is more than 2% faster).  Results never depend on the choice. */
+adept_status adept_autotune_layout(adept_precision precision, uint64_t capacity, const adept_layout* candidates,
+                                   uint32_t n_candidates, uint32_t n_events, const uint32_t* seeds,
+                                   const adept_primary* p, uint64_t n, adept_layout* best_layout,
+                                   adept_launch* best_launch, double* best_ms);
 
 /* Last error message of this context (valid until the next call on it). */
 const char* adept_last_error(const adept_ctx* ctx);

@@ -52,7 +52,7 @@ EXPORTS = [
     "adept_set_admission", "adept_set_instrumented", "adept_set_launch", "adept_get_launch", "adept_inject",
     "adept_inject_device", "adept_step", "adept_run", "adept_tally", "adept_access_counts", "adept_buffer_bytes",
     "adept_stats_get", "adept_dump_tracks", "adept_dump_ring", "adept_reset", "adept_autotune",
-    "adept_set_timing", "adept_last_error", "adept_destroy",
+    "adept_set_timing", "adept_autotune_layout", "adept_last_error", "adept_destroy",
 ]
 
 _lib = None
@@ -90,6 +90,7 @@ def lib():
         "adept_reset": (i32, [P]),
         "adept_autotune": (i32, [P, P, u64, P]),
         "adept_set_timing": (i32, [P, i32]),
+        "adept_autotune_layout": (i32, [i32, u64, P, u32, u32, P, P, u64, P, P, P]),
         "adept_last_error": (ctypes.c_char_p, [P]),
         "adept_destroy": (None, [P]),
     }
@@ -246,6 +247,20 @@ def adept_autotune(ctx, primaries):
 
 def adept_set_timing(ctx, on):
     _check(ctx, lib().adept_set_timing(ctx, int(on)), "adept_set_timing")
+
+
+def adept_autotune_layout(precision, capacity, candidates, seeds, primaries):
+    """candidates: (scheme, mapping, aosoa_lanes) tuples; returns (layout, launch, ms)."""
+    arr = (Layout * len(candidates))(*[Layout(s, m, n) for s, m, n in candidates])
+    sd = np.ascontiguousarray(seeds, dtype=np.uint32)
+    p = np.ascontiguousarray(primaries).view(PRIMARY_DTYPE)
+    best, l, ms = Layout(), Launch(), ctypes.c_double()
+    rc = lib().adept_autotune_layout(precision, int(capacity), ctypes.cast(arr, ctypes.c_void_p), len(candidates),
+                                     len(sd), _ptr(sd), _ptr(p), len(p), ctypes.byref(best), ctypes.byref(l),
+                                     ctypes.byref(ms))
+    _check(None, rc, "adept_autotune_layout")
+    return ((best.scheme, best.mapping, best.aosoa_lanes),
+            {"block": l.block, "grid": l.grid, "graph_iters": l.graph_iters}, ms.value)
 
 
 def adept_last_error(ctx):

@@ -1000,6 +1000,52 @@ adept_status adept_autotune(adept_ctx* c, const adept_primary* p, uint64_t n, ad
   return rc;
 }
 
+adept_status adept_autotune_layout(adept_precision precision, uint64_t capacity, const adept_layout* candidates,
+                                   uint32_t n_candidates, uint32_t n_events, const uint32_t* seeds,
+                                   const adept_primary* p, uint64_t n, adept_layout* best_layout,
+                                   adept_launch* best_launch, double* best_ms) {
+  if (!candidates || n_candidates == 0 || !seeds || n_events == 0 || (!p && n) || !best_layout)
+    return ADEPT_E_INVALID;
+  double best = 1e300;
+  int best_i = -1;
+  adept_launch best_l{};
+  for (uint32_t i = 0; i < n_candidates; ++i) {
+    adept_ctx* c = nullptr;
+    adept_status rc = adept_create(candidates[i], precision, capacity, &c);
+    if (rc) return rc;
+    rc = adept_set_events(c, n_events, seeds);
+    adept_launch l{};
+    if (!rc) rc = adept_autotune(c, p, n, &l);
+    float ms = 0.f;
+    if (!rc) {  // time the tuned configuration once more on a fresh state
+      hipEvent_t e0, e1;
+      if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = ADEPT_E_DEVICE;
+      if (!rc) rc = adept_inject(c, p, n);
+      if (!rc) (void)hipEventRecord(e0, c->stream);
+      uint64_t it = 0;
+      if (!rc) rc = adept_run(c, ~0ull, &it);
+      if (!rc) {
+        (void)hipEventRecord(e1, c->stream);
+        (void)hipEventSynchronize(e1);
+        (void)hipEventElapsedTime(&ms, e0, e1);
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+    }
+    adept_destroy(c);
+    if (rc) return rc;
+    if (ms < best * 0.98) {  // earlier candidates win near-ties
+      best = ms;
+      best_i = (int)i;
+      best_l = l;
+    }
+  }
+  *best_layout = candidates[best_i];
+  if (best_launch) *best_launch = best_l;
+  if (best_ms) *best_ms = best;
+  return ADEPT_OK;
+}
+
 adept_status adept_set_timing(adept_ctx* c, int on) {
   if (!c) return ADEPT_E_INVALID;
   c->timing = on ? 1 : 0;

@@ -287,6 +287,54 @@ struct StatLDS {
   unsigned long long waves, waves_div, surv[3];
 };
 
+// Batched runs (several events) and cell scoring: deposits go through a
+// direct-mapped LDS cache keyed by the flat tally index
+//   [0, 100E) continuous, [100E, 200E) local, [200E, 201E) escaped,
+//   [201E, 202E) rounding, then the cells;
+// a lane whose slot holds another key adds to HBM directly; occupied slots are
+// added to HBM once per block at the end of the kernel.
+constexpr int kCacheBits = 11;
+constexpr int kCacheSlots = 1 << kCacheBits;
+constexpr uint32_t kCacheEmpty = 0xFFFFFFFFu;
+struct TallyCache {
+  uint32_t key[kCacheSlots];
+  double val[kCacheSlots];
+};
+
+__device__ __forceinline__ double* tally_ptr(const KArgs& a, uint32_t key) {
+  const uint32_t E = a.n_events;
+  if (key < 100u * E) return a.cont + key;
+  if (key < 200u * E) return a.cut + (key - 100u * E);
+  if (key < 201u * E) return a.esc + (key - 200u * E);
+  if (key < 202u * E) return a.rnd + (key - 201u * E);
+  return a.cells + (key - 202u * E);
+}
+
+__device__ __forceinline__ void cache_add(const KArgs& a, TallyCache& tc, uint32_t key, double v) {
+  const uint32_t h = (key * 2654435761u) >> (32 - kCacheBits);
+  uint32_t cur = tc.key[h];
+  if (cur == kCacheEmpty) cur = atomicCAS(&tc.key[h], kCacheEmpty, key) == kCacheEmpty ? key : tc.key[h];
+  if (cur == key) {
+    __hip_atomic_fetch_add(&tc.val[h], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  } else {
+    __hip_atomic_fetch_add(tally_ptr(a, key), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__device__ __forceinline__ void cache_init(TallyCache& tc) {
+  for (int i = threadIdx.x; i < kCacheSlots; i += blockDim.x) {
+    tc.key[i] = kCacheEmpty;
+    tc.val[i] = 0.0;
+  }
+}
+
+__device__ __forceinline__ void cache_flush(const KArgs& a, TallyCache& tc) {
+  __syncthreads();
+  for (int i = threadIdx.x; i < kCacheSlots; i += blockDim.x)
+    if (tc.key[i] != kCacheEmpty && tc.val[i] != 0.0)
+      __hip_atomic_fetch_add(tally_ptr(a, tc.key[i]), tc.val[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ void gadd(double* p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -294,31 +342,46 @@ __device__ __forceinline__ void ladd(double* p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-__device__ __forceinline__ void cell_add(const KArgs& a, int v, double x, double y, double e) {
+// Flat index of the cell of (x, y) in the layer of volume v.
+__device__ __forceinline__ uint32_t cell_index(const KArgs& a, int v, double x, double y) {
   const double hx = (0.5 * (double)a.nx) * a.pitch, hy = (0.5 * (double)a.ny) * a.pitch;
   const double fx = floor((x + hx) / a.pitch), fy = floor((y + hy) / a.pitch);
   const uint32_t ix = fx < 0.0 ? 0u : (fx > (double)(a.nx - 1) ? a.nx - 1 : (uint32_t)fx);
   const uint32_t iy = fy < 0.0 ? 0u : (fy > (double)(a.ny - 1) ? a.ny - 1 : (uint32_t)fy);
-  gadd(&a.cells[((unsigned long long)(v >> 1) * a.nx + ix) * a.ny + iy], e);
+  return ((uint32_t)(v >> 1) * a.nx + ix) * a.ny + iy;
 }
 
-// Book one lane's deposits: pre-step volume v, event ev.
-__device__ __forceinline__ void book(const KArgs& a, TallyLDS* tl, uint32_t ev, int v, const Deposits& d,
-                                     const double pos[3]) {
+// Book one lane's deposits: pre-step volume v, event ev.  tl: single-event
+// LDS arrays; tc: LDS cache; neither: direct device atomics.
+__device__ __forceinline__ void book(const KArgs& a, TallyLDS* tl, TallyCache* tc, uint32_t ev, int v,
+                                     const Deposits& d, const double pos[3]) {
   if (tl) {
     if (d.cont != 0.0) ladd(&tl->cont[v], d.cont);
     if (d.cut != 0.0) ladd(&tl->cut[v], d.cut);
     if (d.escaped != 0.0) ladd(&tl->esc, d.escaped);
     if (d.round != 0.0) ladd(&tl->rnd, d.round);
-  } else {
-    if (d.cont != 0.0) gadd(&a.cont[(unsigned long long)ev * kNumVol + v], d.cont);
-    if (d.cut != 0.0) gadd(&a.cut[(unsigned long long)ev * kNumVol + v], d.cut);
-    if (d.escaped != 0.0) gadd(&a.esc[ev], d.escaped);
-    if (d.round != 0.0) gadd(&a.rnd[ev], d.round);
+    return;
   }
+  const uint32_t E = a.n_events;
+  const uint32_t kc = ev * kNumVol + (uint32_t)v, ku = 100u * E + kc, ke = 200u * E + ev, kr = 201u * E + ev;
+  if (tc) {
+    if (d.cont != 0.0) cache_add(a, *tc, kc, d.cont);
+    if (d.cut != 0.0) cache_add(a, *tc, ku, d.cut);
+    if (d.escaped != 0.0) cache_add(a, *tc, ke, d.escaped);
+    if (d.round != 0.0) cache_add(a, *tc, kr, d.round);
+    if (a.cells) {
+      if (d.cont != 0.0) cache_add(a, *tc, 202u * E + cell_index(a, v, d.mid[0], d.mid[1]), d.cont);
+      if (d.cut != 0.0) cache_add(a, *tc, 202u * E + cell_index(a, v, pos[0], pos[1]), d.cut);
+    }
+    return;
+  }
+  if (d.cont != 0.0) gadd(tally_ptr(a, kc), d.cont);
+  if (d.cut != 0.0) gadd(tally_ptr(a, ku), d.cut);
+  if (d.escaped != 0.0) gadd(tally_ptr(a, ke), d.escaped);
+  if (d.round != 0.0) gadd(tally_ptr(a, kr), d.round);
   if (a.cells) {
-    if (d.cont != 0.0) cell_add(a, v, d.mid[0], d.mid[1], d.cont);
-    if (d.cut != 0.0) cell_add(a, v, pos[0], pos[1], d.cut);
+    if (d.cont != 0.0) gadd(a.cells + cell_index(a, v, d.mid[0], d.mid[1]), d.cont);
+    if (d.cut != 0.0) gadd(a.cells + cell_index(a, v, pos[0], pos[1]), d.cut);
   }
 }
 
@@ -416,6 +479,12 @@ __device__ __forceinline__ unsigned long long ceil_div(unsigned long long x, uns
   return (x + y - 1) / y;
 }
 
+// Value of creation slot i (a runtime index) without indexing a register array.
+template <class T>
+__device__ __forceinline__ T sel3(int i, T x0, T x1, T x2) {
+  return i == 0 ? x0 : (i == 1 ? x1 : x2);
+}
+
 // Write one creation (full record) of type d at slot s of physical buffer b.
 template <int MAP, class P, bool INSTR>
 __device__ __forceinline__ void write_creation(const KArgs& a, int d, int b, uint64_t s, bool on,
@@ -423,11 +492,13 @@ __device__ __forceinline__ void write_creation(const KArgs& a, int d, int b, uin
                                                int i) {
   using R = typename P::R;
   const auto A = make_acc<MAP, P, INSTR>(a, d, b, on);
+  const int ds = sel3<int>(i, cr.dsel[0], cr.dsel[1], cr.dsel[2]);
   R dir[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) dir[k] = cr.dsel[i] == 0 ? t.dir[k] : (cr.dsel[i] == 1 ? cr.d[k] : -cr.d[k]);
-  store_full<MAP, P, INSTR>(A, s, t.pos, dir, cr.E[i], (R)-1, cr.id[i], cr.psel[i] ? cr.vid : t.id, t.seed, 0u,
-                            t.vol, t.event);
+  for (int k = 0; k < 3; ++k) dir[k] = ds == 0 ? t.dir[k] : (ds == 1 ? cr.d[k] : -cr.d[k]);
+  const bool ps = sel3<int>(i, cr.psel[0], cr.psel[1], cr.psel[2]) != 0;
+  store_full<MAP, P, INSTR>(A, s, t.pos, dir, sel3(i, cr.E[0], cr.E[1], cr.E[2]), (R)-1,
+                            sel3(i, cr.id[0], cr.id[1], cr.id[2]), ps ? cr.vid : t.id, t.seed, 0u, t.vol, t.event);
 }
 
 // ---------------------------------------------------------------------------
@@ -439,6 +510,7 @@ __global__ void __launch_bounds__(kMaxBlock) ADEPT_STEP_ATTR k_step(const KArgs 
   constexpr int NV = SCHEME == DENSE ? 3 : 9;  // next[3] (+ new[3], kill[3])
   __shared__ Scan<NV> sh;
   __shared__ TallyLDS tl;
+  __shared__ TallyCache tc;
   __shared__ StatLDS ss;
   Ctrl* c = a.ctrl;
   const uint32_t p = c->parity;
@@ -447,7 +519,7 @@ __global__ void __launch_bounds__(kMaxBlock) ADEPT_STEP_ATTR k_step(const KArgs 
   const unsigned long long t0 = ceil_div(n0, T), t1 = ceil_div(n1, T), t2 = ceil_div(n2, T);
   const unsigned long long total = t0 + t1 + t2;
   const bool counting = INSTR && a.instr_on && c->iter < a.instr_last;
-  const bool lds_tally = a.n_events == 1;
+  const bool lds_tally = a.n_events == 1 && !a.cells;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     c->ticket[1 - p] = 0;
     c->ntiles[p] = total;
@@ -461,6 +533,7 @@ __global__ void __launch_bounds__(kMaxBlock) ADEPT_STEP_ATTR k_step(const KArgs 
   }
   if (blockIdx.x >= total) return;
   if (lds_tally) tally_init(tl);
+  else cache_init(tc);
   if (threadIdx.x == 0) ss.waves = ss.waves_div = ss.surv[0] = ss.surv[1] = ss.surv[2] = 0;
   __syncthreads();
   const int lane = __lane_id();
@@ -538,7 +611,7 @@ __global__ void __launch_bounds__(kMaxBlock) ADEPT_STEP_ATTR k_step(const KArgs 
     if (tile == total - 1 && threadIdx.x < NV)
       c->tot[p][threadIdx.x] = sat_add(sh.tile_excl[threadIdx.x], sh.tile_agg[threadIdx.x]);
     if (valid) {
-      book(a, lds_tally ? &tl : nullptr, t.event, v0, dep, t.pos);
+      book(a, lds_tally ? &tl : nullptr, lds_tally ? nullptr : &tc, t.event, v0, dep, t.pos);
       // running position of this lane's next output of each type (next list / dense index)
       uint32_t k0 = lex[0], k1 = lex[1], k2 = lex[2];
       auto next_pos = [&](int d) -> unsigned long long {
@@ -560,14 +633,12 @@ __global__ void __launch_bounds__(kMaxBlock) ADEPT_STEP_ATTR k_step(const KArgs 
             atomicOr(&c->overflow, 1ull);
           }
         }
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          if (i < cr.n) {
-            const int d = cr.type[i];
-            const unsigned long long pos = next_pos(d);
-            if (pos < a.C) write_creation<MAP, P, INSTR>(a, d, bn, pos, counting, t, cr, i);
-            else atomicOr(&c->overflow, 1ull);
-          }
+#pragma unroll 1
+        for (int i = 0; i < cr.n; ++i) {  // one copy of the record store for every creation
+          const int d = sel3<int>(i, cr.type[0], cr.type[1], cr.type[2]);
+          const unsigned long long pos = next_pos(d);
+          if (pos < a.C) write_creation<MAP, P, INSTR>(a, d, bn, pos, counting, t, cr, i);
+          else atomicOr(&c->overflow, 1ull);
         }
       } else {
         uint32_t n0_ = lex[SCHEME == SPARSE ? 3 : 0], n1_ = lex[SCHEME == SPARSE ? 4 : 1],
@@ -582,23 +653,21 @@ __global__ void __launch_bounds__(kMaxBlock) ADEPT_STEP_ATTR k_step(const KArgs 
           const unsigned long long f = sh.tile_excl[6 % NV + (SCHEME == SPARSE ? D : 0)] + lk;
           a.ring[D][(c->head[D] + c->count[D] + f) % a.C] = slot;
         }
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          if (i < cr.n) {
-            const int d = cr.type[i];
-            const unsigned long long pos = next_pos(d);
-            const uint32_t r = d == 0 ? n0_ : (d == 1 ? n1_ : n2_);
-            n0_ += d == 0 ? 1u : 0u;
-            n1_ += d == 1 ? 1u : 0u;
-            n2_ += d == 2 ? 1u : 0u;
-            const unsigned long long j = sh.tile_excl[(SCHEME == SPARSE ? 3 : 0) + d] + r;
-            if (j < c->count[d] && pos < a.C) {
-              const uint32_t s = a.ring[d][(c->head[d] + j) % a.C];
-              write_creation<MAP, P, INSTR>(a, d, 0, s, counting, t, cr, i);
-              a.list[d][1 - p][pos] = s;
-            } else {
-              atomicOr(&c->overflow, 1ull);
-            }
+#pragma unroll 1
+        for (int i = 0; i < cr.n; ++i) {
+          const int d = sel3<int>(i, cr.type[0], cr.type[1], cr.type[2]);
+          const unsigned long long pos = next_pos(d);
+          const uint32_t r = d == 0 ? n0_ : (d == 1 ? n1_ : n2_);
+          n0_ += d == 0 ? 1u : 0u;
+          n1_ += d == 1 ? 1u : 0u;
+          n2_ += d == 2 ? 1u : 0u;
+          const unsigned long long j = sh.tile_excl[(SCHEME == SPARSE ? 3 : 0) + d] + r;
+          if (j < c->count[d] && pos < a.C) {
+            const uint32_t s = a.ring[d][(c->head[d] + j) % a.C];
+            write_creation<MAP, P, INSTR>(a, d, 0, s, counting, t, cr, i);
+            a.list[d][1 - p][pos] = s;
+          } else {
+            atomicOr(&c->overflow, 1ull);
           }
         }
       }
@@ -606,6 +675,7 @@ __global__ void __launch_bounds__(kMaxBlock) ADEPT_STEP_ATTR k_step(const KArgs 
     __syncthreads();  // LDS scan state is reused by the next tile
   }
   if (lds_tally) flush(a, tl);
+  else cache_flush(a, tc);
   __syncthreads();
   if (threadIdx.x == 0) {
     atomicAdd(&c->waves, ss.waves);
@@ -687,7 +757,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_inject(const KArgs a) {
           int kidx = 0;
           annihilate<P>(X, &kidx, 0, cr);
         }
-        book(a, nullptr, ev, t.vol, dep, t.pos);
+        book(a, nullptr, nullptr, ev, t.vol, dep, t.pos);
       } else {
         keep = true;
       }

@@ -330,3 +330,25 @@ def test_autotune_keeps_results(ad, oracle_mod):
     assert sim.stats()["track_steps"] == o.stats()["track_steps"]
     compare_tallies(sim, o, oracle_mod)
     sim.close()
+
+
+def test_layout_autotuner_keeps_results(ad, oracle_mod):
+    """adept_autotune_layout picks one of the candidate layouts; a run in the chosen
+    layout and launch configuration reproduces the oracle's state and deposits."""
+    say("case layout autotuner")
+    wl = workloads.cfg3(n_events=8, max_per_event=12)
+    cands = [(1, 0, 1), (1, 1, 1), (1, 2, 64), (0, 0, 1)]
+    C = 1 << 16
+    layout, launch, ms = ad.adept_autotune_layout(ad.MIXED, C, cands, wl.seeds, wl.primaries)
+    assert layout in cands and ms > 0
+    sim = ad.Sim(layout[0], layout[1], ad.MIXED, C, layout[2], seeds=wl.seeds, launch=launch)
+    sim.inject(wl.primaries)
+    o = oracle_mod.Oracle(layout[0], oracle_mod.MIXED, C, wl.seeds)
+    assert o.inject(wl.primaries) == 0
+    sim.run(30)
+    o.run(30)
+    compare_state(sim, o, 30, layout[0], "autotuned layout")
+    sim.run()
+    o.run()
+    compare_tallies(sim, o, oracle_mod)
+    sim.close()
