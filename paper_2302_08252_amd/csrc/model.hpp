@@ -213,14 +213,31 @@ AD_HD double axis_dist(double p, double d, double lo, double hi) {
   return t > 0.0 ? t : 0.0;
 }
 
-// Distance to the slab boundary; ties resolved z, then x, then y.
+// True if the transverse distance (num / d, num = plane - p) cannot be strictly
+// below s: |num| > s |d| (1 + 2^-40) implies fl(num / d) > s whatever the
+// roundings (each below 2^-53 relative), so the division can be skipped.
+AD_HD bool cannot_beat(double p, double d, double s) {
+  if (d == 0.0) return true;  // +inf never replaces
+  const double num = d > 0.0 ? 200.0 - p : -200.0 - p;
+  const double an = d > 0.0 ? num : -num;
+  const double ad = d > 0.0 ? d : -d;
+  return an > s * ad * (1.0 + 0x1p-40);
+}
+
+// Distance to the slab boundary; ties resolved z, then x, then y.  The x and y
+// distances are only divided out when they might win (same result bit for bit
+// as evaluating all three).
 AD_HD double distance(const double p[3], const double d[3], int v, int* axis) {
-  const double tx = axis_dist(p[0], d[0], -200.0, 200.0);
-  const double ty = axis_dist(p[1], d[1], -200.0, 200.0);
   double s = axis_dist(p[2], d[2], zlo(v), zhi(v));
   int a = 2;
-  if (tx < s) { s = tx; a = 0; }
-  if (ty < s) { s = ty; a = 1; }
+  if (!cannot_beat(p[0], d[0], s)) {
+    const double tx = axis_dist(p[0], d[0], -200.0, 200.0);
+    if (tx < s) { s = tx; a = 0; }
+  }
+  if (!cannot_beat(p[1], d[1], s)) {
+    const double ty = axis_dist(p[1], d[1], -200.0, 200.0);
+    if (ty < s) { s = ty; a = 1; }
+  }
   *axis = a;
   return s;
 }
@@ -490,13 +507,14 @@ AD_HD bool step_photon(Track<typename P::R>& t, Creations<typename P::R>& out, D
   using R = typename P::R;
   using C = Consts<R>;
   const uint32_t n = t.ctr;
-  const U4 a = track_block(t.seed, t.id, n, 0u);
   const Creator<P> X{t.seed, t.id, n, 0};
   int kidx = 0;
   const int v = t.vol, m = v & 1;
   const R E = t.E;
   R nl = t.nl;
-  if (nl < (R)0) nl = -plog<R>(P::uni(a.x));
+  // Random words are drawn only when used: a geometry-limited step of a photon
+  // whose interaction length is already sampled needs none.
+  if (nl < (R)0) nl = -plog<R>(P::uni(track_block(t.seed, t.id, n, 0u).x));
   const bool pair = E > C::pairth;
   const R lam = pair ? C::lpair(m) : C::lcomp(m);
   const R s_phys = nl * lam;
@@ -514,11 +532,12 @@ AD_HD bool step_photon(Track<typename P::R>& t, Creations<typename P::R>& out, D
     return false;
   }
   t.vol = v1;
+  const uint32_t a3 = lim == LIM_PHYS ? track_block(t.seed, t.id, n, 0u).w : 0u;
   if (lim == LIM_PHYS && pair) {
     R T, r;
     two_sum<R>(E, -C::pairth, &T, &r);
     dep.round += (double)r;
-    R Tm = P::uni(a.w) * T;
+    R Tm = P::uni(a3) * T;
     const R Tp = T - Tm;
     Tm = T - Tp;
     create<P>(X, &kidx, ELECTRON, Tm, out, dep);
@@ -528,7 +547,7 @@ AD_HD bool step_photon(Track<typename P::R>& t, Creations<typename P::R>& out, D
   R Enew = E;
   if (lim == LIM_PHYS) {
     const U4 b = track_block(t.seed, t.id, n, 1u);
-    R T = P::uni(a.w) * E;
+    R T = P::uni(a3) * E;
     const R Ep = E - T;
     T = E - Ep;
     create<P>(X, &kidx, ELECTRON, T, out, dep);

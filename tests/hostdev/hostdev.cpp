@@ -108,6 +108,7 @@ uint64_t hd_leaf_addr(int map, int mixed, uint32_t lanes, uint64_t C, uint64_t s
   if (map == MAP_SOA) return leaf_addr<MAP_SOA, false>(m, slot, leaf);
   return leaf_addr<MAP_AOSOA, false>(m, slot, leaf);
 }
+double hd_distance(const double p[3], const double d[3], int v, int* axis) { return distance(p, d, v, axis); }
 uint64_t hd_buffer_bytes(int map, int mixed, uint32_t lanes, uint64_t C) {
   return mixed ? buffer_bytes<true>(map, lanes, C) : buffer_bytes<false>(map, lanes, C);
 }

@@ -47,6 +47,8 @@ def hd(tmp_path_factory):
     L.hd_leaf_addr.restype = ctypes.c_uint64
     L.hd_leaf_addr.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
                                ctypes.c_int]
+    L.hd_distance.restype = ctypes.c_double
+    L.hd_distance.argtypes = [P, P, ctypes.c_int, P]
     L.hd_buffer_bytes.restype = ctypes.c_uint64
     L.hd_buffer_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64]
     return L
@@ -177,3 +179,40 @@ def test_single_step_bitwise(hd, oracle_mod, ptype, mixed):
         n_sec += k - surv.value
     # the sample exercised both outcomes and created secondaries
     assert 0 < n_surv < len(tracks) and n_sec > 50
+
+
+def test_distance_with_skipped_divisions_is_exact(hd, oracle_mod):
+    """The device distance only divides out the transverse planes when they might
+    win; on random and adversarial inputs (near-ties between the planes, points on
+    the walls, axis-parallel and grazing directions) it must equal the oracle's
+    plain evaluation of all three, distance and axis."""
+    rng = np.random.default_rng(21)
+    ax = ctypes.c_int()
+    cases = []
+    for _ in range(20000):
+        v = int(rng.integers(0, 100))
+        l = v >> 1
+        zlo = 8.0 * l + 2.3 if v & 1 else 8.0 * l
+        zhi = 8.0 * (l + 1) if v & 1 else 8.0 * l + 2.3
+        z = rng.uniform(zlo, zhi)
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        # choose x so that the x plane is hit at nearly the same distance as the z plane
+        tz = ((zhi - z) / d[2]) if d[2] > 0 else ((zlo - z) / d[2])
+        if d[0] != 0 and abs(tz * d[0]) < 399:
+            x = (200.0 if d[0] > 0 else -200.0) - tz * d[0] * (1 + rng.choice([0, 1e-16, -1e-16, 1e-12, -1e-12]))
+            x = float(np.clip(x, -200.0, 200.0))
+        else:
+            x = rng.uniform(-200, 200)
+        y = rng.choice([rng.uniform(-200, 200), 200.0, -200.0, x])
+        if rng.random() < 0.1:
+            d = np.array([rng.choice([0.0, 1.0, -1.0]), 0.0, rng.choice([0.0, 1.0])])
+            if not d.any():
+                d[2] = 1.0
+        cases.append((np.array([x, y, z]), d, v))
+    for p, d, v in cases:
+        p = np.ascontiguousarray(p)
+        d = np.ascontiguousarray(d, dtype=np.float64)
+        got = hd.hd_distance(_p(p), _p(d), v, ctypes.byref(ax))
+        want, wax = oracle_mod.distance(p, d, v)
+        assert (got, ax.value) == (want, wax) or (np.isnan(got) and np.isnan(want)), (p, d, v, got, want)
