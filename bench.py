@@ -60,7 +60,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--primaries", type=int, default=100_000)
     ap.add_argument("--capacity-log2", type=int, default=25)
-    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--block", type=int, default=1024)
     ap.add_argument("--graph-iters", type=int, default=32)
     ap.add_argument("--fp64-steps", type=int, default=2, help="timed runs of each FP64 comparison path (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -202,12 +202,12 @@ def batched_section(ad, torch, np, workloads, args):
     kappa = kappa_cfg1()
     C = 1 << 24
     cands = [(1, 0, 1), (1, 1, 1), (1, 2, 16), (1, 2, 64), (1, 2, 256)]
-    sample = wl.primaries[wl.primaries["event"] < 16]
-    layout, launch, _ = ad.adept_autotune_layout(ad.MIXED, 1 << 21, cands, wl.seeds[:16], sample)
+    sample = wl.primaries[wl.primaries["event"] < 4]  # ~2600 primaries: peak ~1e6 photons < 2^22
+    layout, launch, _ = ad.adept_autotune_layout(ad.MIXED, 1 << 22, cands, wl.seeds[:4], sample)
     out = {"workload": wl.description, "capacity_per_type": C, "admission": {"alpha": 0.8, "kappa_per_GeV": kappa},
            "autotuned": {"layout": {"scheme": "dense" if layout[0] else "sparse",
                                     "mapping": ["AoS", "SoA", "AoSoA"][layout[1]], "lanes": layout[2]},
-                         "launch": launch, "tuning_sample": "events 0-15"}}
+                         "launch": launch, "tuning_sample": "events 0-3, capacity 2^22"}}
     sim = ad.Sim(layout[0], layout[1], ad.MIXED, C, layout[2], seeds=wl.seeds, admission=(0.8, kappa), launch=launch)
     dt, it, st = run_once(ad, torch, sim, wl.primaries)
     ts = sum(st["track_steps"])

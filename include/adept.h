@@ -125,7 +125,7 @@ typedef struct {
 
 /* Launch configuration (autotuner output; also settable by hand). */
 typedef struct {
-  uint32_t block;       /* threads per block = compaction tile: power of 2, 64-256 */
+  uint32_t block;       /* threads per block = compaction tile: power of 2, 64-1024 (default 1024) */
   uint32_t grid;        /* resident blocks (0: library default)                  */
   uint32_t graph_iters; /* iterations captured per hipGraph replay (1..256)      */
   uint32_t pad;
@@ -154,11 +154,20 @@ adept_status adept_set_events(adept_ctx* ctx, uint32_t n_events, const uint32_t*
  * centred on the beam axis.  Before bind. */
 adept_status adept_set_scoring(adept_ctx* ctx, uint32_t nx, uint32_t ny, double pitch_mm);
 
-/* Event admission (before each iteration, whole events in order while
- * n_type + ceil(kappa_type * E_event / 1000) <= alpha * capacity for every
- * type; the first waiting event is always admitted when no track is active).
- * When on, adept_inject stages primaries instead of injecting them. */
-adept_status adept_set_admission(adept_ctx* ctx, int on, double alpha, const double kappa[3]);
+/* Event admission before each iteration, a capacity guard for batched runs of
+ * uneven events (Sec. 4 transports primaries in batches; the rule itself is
+ * this library's).  An event's projected peak is ceil(kappa_type * E_event /
+ * 1000) tracks of each type (kappa in tracks per GeV, E in MeV); an admitted
+ * event keeps it reserved for hold_iters iterations, about the time a shower
+ * needs to reach its peak.  Whole events are admitted in order while
+ * n_type + reserved_type + projected peak <= alpha * capacity for every type;
+ * the first waiting event is always admitted when no track is active.  The
+ * rule is a heuristic: a shower that outgrows its projection can still
+ * overflow, which adept_step / adept_run report as ADEPT_E_CAPACITY.
+ * When on, adept_inject stages primaries instead of injecting them.  Before
+ * bind. */
+adept_status adept_set_admission(adept_ctx* ctx, int on, double alpha, const double kappa[3],
+                                 uint64_t hold_iters);
 
 /* Instrumented mode (Sec. 5): count field reads/writes and per-word accesses
  * of every operation that starts while fewer than last_iter iterations are

@@ -81,7 +81,7 @@ def lib():
             "or_destroy": (None, [P]),
             "or_set_scoring": (i32, [P, u32, u32, dbl]),
             "or_set_instrumented": (i32, [P, i32, u64]),
-            "or_set_admission": (i32, [P, i32, dbl, P]),
+            "or_set_admission": (i32, [P, i32, dbl, P, u64]),
             "or_inject": (i32, [P, P, u64]),
             "or_stage": (i32, [P, P, u64]),
             "or_step": (i32, [P, P]),
@@ -166,9 +166,9 @@ class Oracle:
     def set_instrumented(self, on, last_iter):
         self._check(self.L.or_set_instrumented(self.h, int(on), int(last_iter)), "set_instrumented")
 
-    def set_admission(self, on, alpha, kappa):
+    def set_admission(self, on, alpha, kappa, hold_iters=128):
         k = np.ascontiguousarray(kappa, dtype=np.float64)
-        self._check(self.L.or_set_admission(self.h, int(on), float(alpha), _ptr(k)), "set_admission")
+        self._check(self.L.or_set_admission(self.h, int(on), float(alpha), _ptr(k), int(hold_iters)), "set_admission")
 
     def inject(self, prims):
         p = np.ascontiguousarray(prims)

@@ -398,6 +398,10 @@ struct or_sim {
   /* admission */
   int adm_on;
   double alpha, kappa[3];
+  uint64_t hold;           /* iterations an admitted event keeps its projected peak reserved */
+  uint64_t *ev_admit_iter; /* per staged event group: iterations done when it was admitted */
+  uint64_t g_old;          /* first group whose reservation may still be held */
+  double reserved[3];
   or_primary *staged;
   uint64_t n_staged;
   uint64_t *ev_first, *ev_count; /* per staged event group */
@@ -468,6 +472,7 @@ void or_destroy(or_sim *S) {
   free(S->seeds);
   free(S->cont); free(S->cut); free(S->escaped); free(S->round); free(S->ein); free(S->cells);
   free(S->staged); free(S->ev_first); free(S->ev_count); free(S->ev_energy); free(S->ev_id);
+  free(S->ev_admit_iter);
   free(S->out);
   free(S);
 }
@@ -495,9 +500,10 @@ int or_set_instrumented(or_sim *S, int on, uint64_t last_iter) {
   return OR_OK;
 }
 
-int or_set_admission(or_sim *S, int on, double alpha, const double kappa[3]) {
+int or_set_admission(or_sim *S, int on, double alpha, const double kappa[3], uint64_t hold_iters) {
   S->adm_on = on;
   S->alpha = alpha;
+  S->hold = hold_iters;
   for (int t = 0; t < 3; ++t) S->kappa[t] = kappa[t];
   return OR_OK;
 }
@@ -1108,6 +1114,7 @@ int or_stage(or_sim *S, const or_primary *p, uint64_t n) {
     if (i > 0 && p[i].event < p[i - 1].event) return OR_E_INVALID;
   }
   free(S->staged); free(S->ev_first); free(S->ev_count); free(S->ev_energy); free(S->ev_id);
+  free(S->ev_admit_iter);
   S->staged = (or_primary *)malloc(n * sizeof(or_primary) + 1);
   memcpy(S->staged, p, n * sizeof(or_primary));
   S->n_staged = n;
@@ -1118,6 +1125,9 @@ int or_stage(or_sim *S, const or_primary *p, uint64_t n) {
   S->ev_count = (uint64_t *)calloc(g + 1, sizeof(uint64_t));
   S->ev_energy = (double *)calloc(g + 1, sizeof(double));
   S->ev_id = (uint32_t *)calloc(g + 1, sizeof(uint32_t));
+  S->ev_admit_iter = (uint64_t *)calloc(g + 1, sizeof(uint64_t));
+  S->g_old = 0;
+  for (int t = 0; t < 3; ++t) S->reserved[t] = 0.0;
   g = 0;
   for (uint64_t i = 0; i < n; ++i) {
     if (i == 0 || p[i].event != p[i - 1].event) {
@@ -1133,13 +1143,23 @@ int or_stage(or_sim *S, const or_primary *p, uint64_t n) {
   return OR_OK;
 }
 
-/* Admission before an iteration: whole events in order while, for every type,
- * n + ceil(kappa * E_event / 1000) <= alpha * C (projections of the events
- * admitted in this round accumulate); with no active track, the first waiting
- * event is always admitted. */
+/* Projected peak of an event group: ceil(kappa * E_event / 1000) tracks per type. */
+static double need_of(const or_sim *S, uint64_t g, int t) { return ceil(S->kappa[t] * S->ev_energy[g] / 1000.0); }
+
+/* Admission before an iteration: an admitted event keeps its projected peak
+ * reserved for `hold` iterations (about the time its shower needs to peak).
+ * Whole events are admitted in order while, for every type,
+ * n + reserved + projected peak <= alpha * C; with no active track, the first
+ * waiting event is always admitted. */
 static int admit(or_sim *S) {
   if (!S->adm_on || S->next_group >= S->n_groups) return OR_OK;
-  double run[3] = {(double)S->n[0], (double)S->n[1], (double)S->n[2]};
+  const uint64_t now = S->iter;
+  while (S->g_old < S->next_group && S->ev_admit_iter[S->g_old] + S->hold <= now) {
+    for (int t = 0; t < 3; ++t) S->reserved[t] = S->reserved[t] - need_of(S, S->g_old, t);
+    S->g_old += 1;
+  }
+  double run[3];
+  for (int t = 0; t < 3; ++t) run[t] = (double)S->n[t] + S->reserved[t];
   const int none_active = (S->n[0] + S->n[1] + S->n[2]) == 0;
   const double limit = S->alpha * (double)S->C;
   uint64_t g0 = S->next_group, g = g0;
@@ -1147,11 +1167,15 @@ static int admit(or_sim *S) {
     double need[3];
     int fits = 1;
     for (int t = 0; t < 3; ++t) {
-      need[t] = ceil(S->kappa[t] * S->ev_energy[g] / 1000.0);
+      need[t] = need_of(S, g, t);
       if (!(run[t] + need[t] <= limit)) fits = 0;
     }
     if (!fits && !(none_active && g == g0)) break;
-    for (int t = 0; t < 3; ++t) run[t] = run[t] + need[t];
+    for (int t = 0; t < 3; ++t) {
+      run[t] = run[t] + need[t];
+      S->reserved[t] = S->reserved[t] + need[t];
+    }
+    S->ev_admit_iter[g] = now;
     g += 1;
   }
   if (g == g0) return OR_OK;

@@ -79,7 +79,7 @@ or_sim *or_create(int scheme, int precision, uint64_t capacity, uint32_t n_event
 void or_destroy(or_sim *s);
 int or_set_scoring(or_sim *s, uint32_t nx, uint32_t ny, double pitch);
 int or_set_instrumented(or_sim *s, int on, uint64_t last_iter);
-int or_set_admission(or_sim *s, int on, double alpha, const double kappa[3]);
+int or_set_admission(or_sim *s, int on, double alpha, const double kappa[3], uint64_t hold_iters);
 int or_inject(or_sim *s, const or_primary *p, uint64_t n);
 int or_stage(or_sim *s, const or_primary *p, uint64_t n);
 int or_step(or_sim *s, uint64_t next_counts[3]);

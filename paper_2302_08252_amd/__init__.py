@@ -73,7 +73,7 @@ def lib():
         "adept_bind": (i32, [P, P, sz, P]),
         "adept_set_events": (i32, [P, u32, P]),
         "adept_set_scoring": (i32, [P, u32, u32, dbl]),
-        "adept_set_admission": (i32, [P, i32, dbl, P]),
+        "adept_set_admission": (i32, [P, i32, dbl, P, u64]),
         "adept_set_instrumented": (i32, [P, i32, u64]),
         "adept_set_launch": (i32, [P, P]),
         "adept_get_launch": (i32, [P, P]),
@@ -144,16 +144,17 @@ def adept_set_scoring(ctx, nx, ny, pitch):
     _check(ctx, lib().adept_set_scoring(ctx, nx, ny, pitch), "adept_set_scoring")
 
 
-def adept_set_admission(ctx, on, alpha, kappa):
+def adept_set_admission(ctx, on, alpha, kappa, hold_iters=128):
     k = np.ascontiguousarray(kappa, dtype=np.float64)
-    _check(ctx, lib().adept_set_admission(ctx, int(on), float(alpha), _ptr(k)), "adept_set_admission")
+    _check(ctx, lib().adept_set_admission(ctx, int(on), float(alpha), _ptr(k), int(hold_iters)),
+           "adept_set_admission")
 
 
 def adept_set_instrumented(ctx, on, last_iter):
     _check(ctx, lib().adept_set_instrumented(ctx, int(on), int(last_iter)), "adept_set_instrumented")
 
 
-def adept_set_launch(ctx, block=256, grid=0, graph_iters=32):
+def adept_set_launch(ctx, block=1024, grid=0, graph_iters=32):
     l = Launch(block, grid, graph_iters, 0)
     _check(ctx, lib().adept_set_launch(ctx, ctypes.byref(l)), "adept_set_launch")
 
@@ -289,7 +290,7 @@ class Sim:
                 adept_set_scoring(self.ctx, *scoring)
                 self.nx, self.ny = scoring[0], scoring[1]
             if admission:
-                adept_set_admission(self.ctx, True, admission[0], admission[1])
+                adept_set_admission(self.ctx, True, *admission)
             if instrumented is not None:
                 adept_set_instrumented(self.ctx, True, instrumented)
             if launch:

@@ -30,7 +30,7 @@ def _newest(paths):
 def build(force=True, jobs=None, verbose=False, defines=(), lib_path=LIB, build_dir=BUILD):
     """Compile every HIP translation unit and link libadept.so.  With force=False
     an up-to-date library is kept.  defines: extra -D tuning macros
-    (ADEPT_MAX_BLOCK, ADEPT_WAVES_PER_EU, ADEPT_NT), with lib_path / build_dir for
+    (ADEPT_WAVES_PER_EU, ADEPT_NT), with lib_path / build_dir for
     a separate build."""
     LIB_OUT, BDIR = lib_path, build_dir
     os.makedirs(BDIR, exist_ok=True)

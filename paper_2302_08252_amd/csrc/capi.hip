@@ -81,16 +81,27 @@ __global__ void k_epilogue(const KArgs a) {
   m->done = (tot[0] + tot[1] + tot[2] == 0 && !staged_left) ? 1ull : 0ull;
 }
 
-// Event admission before an iteration (one thread; binary64 arithmetic).
+// Event admission before an iteration (one thread; binary64 arithmetic).  An
+// admitted group keeps its projected peak ceil(kappa * E / 1000) reserved for
+// `hold` iterations; groups are admitted in order while, for every type,
+// active + reserved + projected peak <= alpha * C (the first waiting group
+// always goes in when nothing is active).
 __global__ void k_admit(const KArgs a) {
   if (threadIdx.x != 0) return;
   Ctrl* c = a.ctrl;
+  EventGroup* groups = const_cast<EventGroup*>(a.groups);
   c->inj_begin = c->inj_end = 0;
   if (c->error) return;
   const uint32_t p = c->parity;
   c->had_staged = c->next_group < c->n_groups ? 1u : 0u;
   if (!c->had_staged) return;
-  double run[3] = {(double)c->n[p][0], (double)c->n[p][1], (double)c->n[p][2]};
+  const unsigned long long now = c->iter;
+  while (c->g_old < c->next_group && groups[c->g_old].admit_iter + a.hold <= now) {
+    for (int d = 0; d < 3; ++d) c->reserved[d] = c->reserved[d] - ceil(a.kappa[d] * groups[c->g_old].energy / 1000.0);
+    c->g_old += 1;
+  }
+  double run[3];
+  for (int d = 0; d < 3; ++d) run[d] = (double)c->n[p][d] + c->reserved[d];
   const bool none_active = c->n[p][0] + c->n[p][1] + c->n[p][2] == 0;
   const double limit = a.alpha * (double)a.C;
   const unsigned long long g0 = c->next_group;
@@ -99,16 +110,20 @@ __global__ void k_admit(const KArgs a) {
     double need[3];
     bool fits = true;
     for (int d = 0; d < 3; ++d) {
-      need[d] = ceil(a.kappa[d] * a.groups[g].energy / 1000.0);
+      need[d] = ceil(a.kappa[d] * groups[g].energy / 1000.0);
       if (!(run[d] + need[d] <= limit)) fits = false;
     }
     if (!fits && !(none_active && g == g0)) break;
-    for (int d = 0; d < 3; ++d) run[d] = run[d] + need[d];
+    for (int d = 0; d < 3; ++d) {
+      run[d] = run[d] + need[d];
+      c->reserved[d] = c->reserved[d] + need[d];
+    }
+    groups[g].admit_iter = now;
     g += 1;
   }
   if (g > g0) {
-    c->inj_begin = a.groups[g0].first;
-    c->inj_end = a.groups[g - 1].first + a.groups[g - 1].count;
+    c->inj_begin = groups[g0].first;
+    c->inj_end = groups[g - 1].first + groups[g - 1].count;
     c->next_group = g;
   }
 }
@@ -255,9 +270,10 @@ struct adept_ctx {
   double pitch = 0.0;
   int adm_on = 0;
   double alpha = 0.8, kappa[3] = {0, 0, 0};
+  unsigned long long hold = 128;
   int instr_on = 0;
   unsigned long long instr_last = 0;
-  adept_launch launch{256, 0, 32, 0};
+  adept_launch launch{1024, 0, 32, 0};
   // device
   int device = 0, num_cu = 0;
   void* arena = nullptr;
@@ -400,6 +416,7 @@ void fill_args(adept_ctx* c) {
   a.adm_on = c->adm_on;
   a.alpha = c->alpha;
   for (int d = 0; d < 3; ++d) a.kappa[d] = c->kappa[d];
+  a.hold = c->hold;
   a.count_empty = 1;
   c->scratch = (double*)(A + P.scratch);
   c->buf_bytes = buf_bytes_of(c);
@@ -557,7 +574,10 @@ adept_status upload_staged(adept_ctx* c) {
   // the group table replaces any earlier one: admission restarts at group 0
   Ctrl* dc = c->args.ctrl;
   const unsigned long long zero = 0, ng = g.size();
+  const double none[3] = {0.0, 0.0, 0.0};
   HIPCHK(hipMemcpyAsync(&dc->next_group, &zero, 8, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(&dc->g_old, &zero, 8, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(dc->reserved, none, sizeof(none), hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(&dc->n_groups, &ng, 8, hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   c->staged_dirty = false;
@@ -656,11 +676,13 @@ adept_status adept_set_scoring(adept_ctx* c, uint32_t nx, uint32_t ny, double pi
   return ADEPT_OK;
 }
 
-adept_status adept_set_admission(adept_ctx* c, int on, double alpha, const double kappa[3]) {
+adept_status adept_set_admission(adept_ctx* c, int on, double alpha, const double kappa[3],
+                                 uint64_t hold_iters) {
   if (!c || (on && (!kappa || !(alpha > 0.0)))) return ADEPT_E_INVALID;
   if (c->state != CREATED) return fail(c, ADEPT_E_STATE, "set_admission after bind");
   c->adm_on = on ? 1 : 0;
   c->alpha = alpha;
+  c->hold = hold_iters;
   for (int d = 0; d < 3; ++d) c->kappa[d] = kappa ? kappa[d] : 0.0;
   return ADEPT_OK;
 }
@@ -959,7 +981,7 @@ adept_status adept_autotune(adept_ctx* c, const adept_primary* p, uint64_t n, ad
   adept_status rc = ensure_ready(c);
   if (rc) return rc;
   const adept_launch saved = c->launch;
-  const uint32_t blocks[3] = {64, 128, 256};
+  const uint32_t blocks[5] = {64, 128, 256, 512, 1024};
   const uint32_t ks[2] = {16, 64};
   adept_launch best = saved;
   float best_ms = 1e30f;

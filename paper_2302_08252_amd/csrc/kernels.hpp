@@ -26,9 +26,6 @@
 
 namespace adept {
 
-#ifndef ADEPT_MAX_BLOCK
-#define ADEPT_MAX_BLOCK 256
-#endif
 // Occupancy hint for the step kernel (minimum waves per SIMD; 0: none).
 #ifndef ADEPT_WAVES_PER_EU
 #define ADEPT_WAVES_PER_EU 0
@@ -39,7 +36,11 @@ namespace adept {
 #define ADEPT_STEP_ATTR
 #endif
 
-constexpr int kMaxBlock = ADEPT_MAX_BLOCK;
+// Blocks (= compaction tiles) of 64 to 1024 threads.  The step kernel exists in
+// two register budgets: launch bounds 256 for tiles up to 256 tracks, and 1024
+// (128 VGPRs, four waves per SIMD) for 512 and 1024: larger tiles spread the
+// ticket and look-back latency over more tracks.
+constexpr int kMaxBlock = 1024;
 constexpr int kMaxWaves = kMaxBlock / 64;
 constexpr unsigned kMaxGrid = 8192;          // largest grid of the step kernel
 constexpr int kRowLen = 2 * 100 + 2;         // continuous[100], local[100], escaped, rounding
@@ -61,6 +62,8 @@ struct Ctrl {
   unsigned long long inj_ticket[2], inj_ntiles[2], inj_tot[3];
   unsigned long long inj_begin, inj_end;
   unsigned long long next_group, n_groups;
+  unsigned long long g_old;         // admission: first group whose reservation may still be held
+  double reserved[3];               // admission: projected peaks of recently admitted groups
   unsigned int parity, inj_parity;
   int error;
   unsigned int had_staged;
@@ -80,6 +83,7 @@ struct HostMirror {
 struct EventGroup {
   unsigned long long first, count;
   double energy;
+  unsigned long long admit_iter;  // iterations done when the group was admitted
 };
 
 // Everything a kernel needs, by value.
@@ -116,6 +120,7 @@ struct KArgs {
   int adm_on;
   double alpha;
   double kappa[3];
+  unsigned long long hold;
   // epilogue behaviour: 1 = an iteration with nothing active still counts
   int count_empty;
   int pad2;
@@ -504,8 +509,8 @@ __device__ __forceinline__ void write_creation(const KArgs& a, int d, int b, uin
 // ---------------------------------------------------------------------------
 // The fused step kernel.
 // ---------------------------------------------------------------------------
-template <int SCHEME, int MAP, class P, bool INSTR>
-__global__ void __launch_bounds__(kMaxBlock) ADEPT_STEP_ATTR k_step(const KArgs a) {
+template <int SCHEME, int MAP, class P, bool INSTR, int LB>
+__global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
   using R = typename P::R;
   constexpr int NV = SCHEME == DENSE ? 3 : 9;  // next[3] (+ new[3], kill[3])
   __shared__ Scan<NV> sh;
@@ -537,19 +542,16 @@ __global__ void __launch_bounds__(kMaxBlock) ADEPT_STEP_ATTR k_step(const KArgs 
   if (threadIdx.x == 0) ss.waves = ss.waves_div = ss.surv[0] = ss.surv[1] = ss.surv[2] = 0;
   __syncthreads();
   const int lane = __lane_id();
-  // The ticket of the block's next tile is taken while the current tile is
-  // processed, so the atomic's latency overlaps the tile's work.  Holding it
-  // early cannot block anybody: this block reaches that tile next.
-  unsigned long long my_next = 0;  // thread 0: ticket of the following tile, kept in a register
+  // The next tile's ticket is taken once this tile's look-back is done, so the
+  // atomic overlaps the stores of the write phase.  (Taking it any earlier
+  // would make every later tile's look-back wait for this block.)
   if (threadIdx.x == 0)
-    my_next = __hip_atomic_fetch_add(&c->ticket[p], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    sh.ticket = __hip_atomic_fetch_add(&c->ticket[p], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  unsigned long long my_next = 0;
   for (;;) {
-    if (threadIdx.x == 0) sh.ticket = my_next;
-    __syncthreads();
     const unsigned long long tile = sh.ticket;
     if (tile >= total) break;
-    if (threadIdx.x == 0)
-      my_next = __hip_atomic_fetch_add(&c->ticket[p], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int D;
     unsigned long long lt, nD;
     if (tile < t0) { D = ELECTRON; lt = tile; nD = n0; }
@@ -572,6 +574,7 @@ __global__ void __launch_bounds__(kMaxBlock) ADEPT_STEP_ATTR k_step(const KArgs 
       v0 = t.vol;
       surv = D == GAMMA ? step_photon<P>(t, cr, dep) : step_charged<P>(t, D, cr, dep);
       lim_code = (surv ? 1 : 0) | (cr.n << 1);
+      book(a, lds_tally ? &tl : nullptr, lds_tally ? nullptr : &tc, t.event, v0, dep, t.pos);
     }
     {  // divergence diagnostic: lanes of a wavefront that disagree on the outcome
       const unsigned long long vm = __ballot(valid);
@@ -604,14 +607,16 @@ __global__ void __launch_bounds__(kMaxBlock) ADEPT_STEP_ATTR k_step(const KArgs 
         }
       }
     }
+    const int ncr = cr.n;
     uint32_t lex[NV];
     block_scan<NV>(cnt, lex, sh);
     lookback<NV>(a.desc[p], tile, sh, &c->overflow);
     __syncthreads();
     if (tile == total - 1 && threadIdx.x < NV)
       c->tot[p][threadIdx.x] = sat_add(sh.tile_excl[threadIdx.x], sh.tile_agg[threadIdx.x]);
+    if (threadIdx.x == 0)
+      my_next = __hip_atomic_fetch_add(&c->ticket[p], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (valid) {
-      book(a, lds_tally ? &tl : nullptr, lds_tally ? nullptr : &tc, t.event, v0, dep, t.pos);
       // running position of this lane's next output of each type (next list / dense index)
       uint32_t k0 = lex[0], k1 = lex[1], k2 = lex[2];
       auto next_pos = [&](int d) -> unsigned long long {
@@ -634,7 +639,7 @@ __global__ void __launch_bounds__(kMaxBlock) ADEPT_STEP_ATTR k_step(const KArgs 
           }
         }
 #pragma unroll 1
-        for (int i = 0; i < cr.n; ++i) {  // one copy of the record store for every creation
+        for (int i = 0; i < ncr; ++i) {  // one copy of the record store for every creation
           const int d = sel3<int>(i, cr.type[0], cr.type[1], cr.type[2]);
           const unsigned long long pos = next_pos(d);
           if (pos < a.C) write_creation<MAP, P, INSTR>(a, d, bn, pos, counting, t, cr, i);
@@ -654,7 +659,7 @@ __global__ void __launch_bounds__(kMaxBlock) ADEPT_STEP_ATTR k_step(const KArgs 
           a.ring[D][(c->head[D] + c->count[D] + f) % a.C] = slot;
         }
 #pragma unroll 1
-        for (int i = 0; i < cr.n; ++i) {
+        for (int i = 0; i < ncr; ++i) {
           const int d = sel3<int>(i, cr.type[0], cr.type[1], cr.type[2]);
           const unsigned long long pos = next_pos(d);
           const uint32_t r = d == 0 ? n0_ : (d == 1 ? n1_ : n2_);
@@ -673,6 +678,8 @@ __global__ void __launch_bounds__(kMaxBlock) ADEPT_STEP_ATTR k_step(const KArgs 
       }
     }
     __syncthreads();  // LDS scan state is reused by the next tile
+    if (threadIdx.x == 0) sh.ticket = my_next;
+    __syncthreads();
   }
   if (lds_tally) flush(a, tl);
   else cache_flush(a, tc);
@@ -872,7 +879,10 @@ struct Ops {
 template <int SCHEME, int MAP, class P, bool INSTR>
 struct Variant {
   static void step(const KArgs& a, unsigned grid, unsigned block, hipStream_t s) {
-    hipLaunchKernelGGL((k_step<SCHEME, MAP, P, INSTR>), dim3(grid), dim3(block), 0, s, a);
+    if (block <= 256)
+      hipLaunchKernelGGL((k_step<SCHEME, MAP, P, INSTR, 256>), dim3(grid), dim3(block), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_step<SCHEME, MAP, P, INSTR, 1024>), dim3(grid), dim3(block), 0, s, a);
   }
   static void inject(const KArgs& a, unsigned grid, unsigned block, hipStream_t s) {
     hipLaunchKernelGGL((k_inject<SCHEME, MAP, P, INSTR>), dim3(grid), dim3(block), 0, s, a);

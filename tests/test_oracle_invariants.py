@@ -12,6 +12,7 @@
 * the mixed-precision policy changes few discrete decisions.
 """
 import collections
+import math
 
 import numpy as np
 import pytest
@@ -283,3 +284,64 @@ def test_admission_properties(oracle_mod):
     assert it > solo.stats()["iterations"]
     assert np.allclose(b.tally(oracle_mod.T_LAYER), solo.tally(oracle_mod.T_LAYER), rtol=1e-12, atol=1e-12)
     assert b.stats()["track_steps"] == solo.stats()["track_steps"]
+
+
+def _admission_trace(oracle_mod, wl, kappa, alpha, C, hold):
+    """Step the oracle one iteration at a time; return, per iteration, the counts
+    before it and the events whose energy entered during it."""
+    o = oracle_mod.Oracle(oracle_mod.DENSE, 0, C, wl.seeds)
+    o.set_admission(True, alpha, kappa, hold)
+    o.stage(wl.primaries)
+    seen = np.zeros(len(wl.seeds), dtype=bool)
+    trace = []
+    for _ in range(5000):
+        before = o.counts().copy()
+        rc, n = o.step()
+        assert rc == 0
+        ein = o.tally(oracle_mod.T_EIN)
+        new = np.nonzero((ein > 0) & ~seen)[0]
+        seen |= ein > 0
+        trace.append((before, list(new)))
+        if n.sum() == 0 and seen.all():
+            break
+    return o, trace
+
+
+def test_admission_reservation_limits(oracle_mod):
+    """The reservation window at its two ends: with an unbounded hold nothing is
+    ever released, so after the first batch events enter one at a time and only
+    when no track is active; with hold 0 every admission satisfies
+    n + sum of projected peaks <= alpha * C on the counts of that iteration.
+    Per-event tallies never depend on the hold."""
+    wl = workloads.cfg3(n_events=12, max_per_event=2)
+    kappa = [4.0, 4.0, 40.0]
+    alpha, C = 0.5, 4096
+    E = wl.event_energy()
+    need = lambda e: [math.ceil(k * E[e] / 1000.0) for k in kappa]
+    inf, trace_inf = _admission_trace(oracle_mod, wl, kappa, alpha, C, 1 << 62)
+    zero, trace_zero = _admission_trace(oracle_mod, wl, kappa, alpha, C, 0)
+    first = True
+    for before, new in trace_inf:
+        if not new:
+            continue
+        if first:
+            first = False
+            tot = [sum(need(e)[d] for e in new) for d in range(3)]
+            assert all(t <= alpha * C for t in tot) or len(new) == 1
+        else:
+            assert before.sum() == 0 and len(new) == 1, (before, new)
+    batches = 0
+    for before, new in trace_zero:
+        if not new:
+            continue
+        batches += 1
+        tot = [before[d] + sum(need(e)[d] for e in new) for d in range(3)]
+        assert all(t <= alpha * C for t in tot) or (before.sum() == 0 and len(new) == 1), (before, new)
+    assert batches >= 2
+    # events admitted in order, each exactly once
+    order = [e for _, new in trace_inf for e in new]
+    assert order == list(range(len(wl.seeds)))
+    assert [e for _, new in trace_zero for e in new] == order
+    assert np.allclose(inf.tally(oracle_mod.T_LAYER), zero.tally(oracle_mod.T_LAYER), rtol=1e-12, atol=1e-12)
+    assert inf.stats()["track_steps"] == zero.stats()["track_steps"]
+    assert len(trace_inf) > len(trace_zero)
