@@ -403,6 +403,10 @@ void fill_args(adept_ctx* c) {
   a.nx = c->nx;
   a.ny = c->ny;
   a.pitch = c->pitch;
+  a.cell_hx = (0.5 * (double)c->nx) * c->pitch;
+  a.cell_hy = (0.5 * (double)c->ny) * c->pitch;
+  a.cell_xmax = (double)c->nx - 1.0;
+  a.cell_ymax = (double)c->ny - 1.0;
   a.staged = c->staged;
   a.groups = c->groups;
   a.seeds = (const uint32_t*)(A + P.seeds);

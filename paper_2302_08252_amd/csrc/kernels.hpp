@@ -104,6 +104,8 @@ struct KArgs {
   double* rows;                // single-event runs: one tally row per block index, kRowLen doubles
   uint32_t nx, ny;
   double pitch;
+  double cell_hx, cell_hy;     // (0.5 * nx) * pitch, (0.5 * ny) * pitch
+  double cell_xmax, cell_ymax; // nx - 1, ny - 1
   const adept_primary* staged; // primaries waiting for injection
   const EventGroup* groups;
   const uint32_t* seeds;
@@ -133,10 +135,41 @@ __device__ __forceinline__ void st_agent(unsigned long long* p, unsigned long lo
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Cross-lane sums with DPP row shifts (no LDS permute, no per-lane addresses):
+// row_shr<K>(x) is x of lane (l - K) when that lane lies in l's row of 16, else 0.
+template <int K>
+__device__ __forceinline__ uint32_t row_shr(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x110 + K, 0xf, 0xf, false);
+}
+template <int K>
+__device__ __forceinline__ unsigned long long row_shr(unsigned long long x) {
+  const uint32_t lo = row_shr<K>((uint32_t)x), hi = row_shr<K>((uint32_t)(x >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+template <class T>
+__device__ __forceinline__ T row_scan(T x) {  // inclusive, within each row of 16 lanes
+  x += row_shr<1>(x);
+  x += row_shr<2>(x);
+  x += row_shr<4>(x);
+  x += row_shr<8>(x);
+  return x;
+}
+__device__ __forceinline__ uint32_t lane_value(uint32_t x, int l) { return __builtin_amdgcn_readlane(x, l); }
+__device__ __forceinline__ unsigned long long lane_value(unsigned long long x, int l) {
+  return ((unsigned long long)__builtin_amdgcn_readlane((uint32_t)(x >> 32), l) << 32) |
+         __builtin_amdgcn_readlane((uint32_t)x, l);
+}
+// Inclusive scan over the 64 lanes of a wavefront (every lane active).
+__device__ __forceinline__ uint32_t wave_scan(uint32_t x) {
+  x = row_scan(x);
+  const uint32_t r0 = lane_value(x, 15), r1 = lane_value(x, 31), r2 = lane_value(x, 47);
+  const int row = __lane_id() >> 4;
+  return x + (row >= 1 ? r0 : 0u) + (row >= 2 ? r1 : 0u) + (row >= 3 ? r2 : 0u);
+}
+// Sum over the 64 lanes of a wavefront (every lane active); uniform result.
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v = row_scan(v);
+  return lane_value(v, 15) + lane_value(v, 31) + lane_value(v, 47) + lane_value(v, 63);
 }
 
 // ---------------------------------------------------------------------------
@@ -150,8 +183,8 @@ constexpr unsigned long long kStA = 1ull << 62, kStP = 2ull << 62;
 
 template <int NV>
 struct Scan {
-  static constexpr int W = (NV + 3) / 4;
-  unsigned long long wave_tot[kMaxWaves][W];
+  static constexpr int W = (NV + 2) / 3;  // 32-bit words of three 10-bit fields
+  uint32_t wave_tot[kMaxWaves][W];
   unsigned long long tile_excl[NV];
   unsigned long long tile_agg[NV];
   unsigned long long ticket;
@@ -162,24 +195,28 @@ __device__ __forceinline__ unsigned long long sat_add(unsigned long long a, unsi
   return s > kSat ? kSat : s;
 }
 
+// Three 10-bit fields to three 16-bit fields of a 64-bit word.
+__device__ __forceinline__ unsigned long long widen3(uint32_t t) {
+  return (unsigned long long)(t & 0x3FFu) | ((unsigned long long)(t & 0xFFC00u) << 6) |
+         ((unsigned long long)(t & 0x3FF00000u) << 12);
+}
+
 // Block-exclusive prefix per lane (lex) and block aggregate (agg, in LDS).
+// Per-lane counts are below 5 and a wavefront's totals below 2^10, so a
+// wavefront scans three counts per 32-bit word; sums over wavefronts (below
+// 2^13) use 16-bit fields.
 template <int NV>
 __device__ __forceinline__ void block_scan(const uint32_t cnt[NV], uint32_t lex[NV], Scan<NV>& sh) {
   constexpr int W = Scan<NV>::W;
   const int lane = __lane_id(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  unsigned long long x[W], inc[W];
+  uint32_t x[W], inc[W];
 #pragma unroll
   for (int w = 0; w < W; ++w) {
     x[w] = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (4 * w + k < NV) x[w] |= (unsigned long long)cnt[4 * w + k] << (16 * k);
-    inc[w] = x[w];
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const unsigned long long y = __shfl_up(inc[w], o, 64);
-      if (lane >= o) inc[w] += y;
-    }
+    for (int k = 0; k < 3; ++k)
+      if (3 * w + k < NV) x[w] |= cnt[3 * w + k] << (10 * k);
+    inc[w] = wave_scan(x[w]);
     if (lane == 63) sh.wave_tot[wave][w] = inc[w];
   }
   __syncthreads();
@@ -187,16 +224,16 @@ __device__ __forceinline__ void block_scan(const uint32_t cnt[NV], uint32_t lex[
   for (int w = 0; w < W; ++w) {
     unsigned long long before = 0, all = 0;
     for (int j = 0; j < nw; ++j) {
-      const unsigned long long t = sh.wave_tot[j][w];
+      const unsigned long long t = widen3(sh.wave_tot[j][w]);
       if (j < wave) before += t;
       all += t;
     }
-    const unsigned long long ex = before + inc[w] - x[w];
+    const unsigned long long ex = before + widen3(inc[w] - x[w]);
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (4 * w + k < NV) {
-        lex[4 * w + k] = (uint32_t)((ex >> (16 * k)) & 0xFFFF);
-        if (threadIdx.x == 0) sh.tile_agg[4 * w + k] = (all >> (16 * k)) & 0xFFFF;
+    for (int k = 0; k < 3; ++k)
+      if (3 * w + k < NV) {
+        lex[3 * w + k] = (uint32_t)((ex >> (16 * k)) & 0xFFFF);
+        if (threadIdx.x == 0) sh.tile_agg[3 * w + k] = (all >> (16 * k)) & 0xFFFF;
       }
   }
   __syncthreads();
@@ -349,10 +386,9 @@ __device__ __forceinline__ void ladd(double* p, double v) {
 
 // Flat index of the cell of (x, y) in the layer of volume v.
 __device__ __forceinline__ uint32_t cell_index(const KArgs& a, int v, double x, double y) {
-  const double hx = (0.5 * (double)a.nx) * a.pitch, hy = (0.5 * (double)a.ny) * a.pitch;
-  const double fx = floor((x + hx) / a.pitch), fy = floor((y + hy) / a.pitch);
-  const uint32_t ix = fx < 0.0 ? 0u : (fx > (double)(a.nx - 1) ? a.nx - 1 : (uint32_t)fx);
-  const uint32_t iy = fy < 0.0 ? 0u : (fy > (double)(a.ny - 1) ? a.ny - 1 : (uint32_t)fy);
+  const double fx = floor((x + a.cell_hx) / a.pitch), fy = floor((y + a.cell_hy) / a.pitch);
+  const uint32_t ix = fx < 0.0 ? 0u : (fx > a.cell_xmax ? a.nx - 1 : (uint32_t)fx);
+  const uint32_t iy = fy < 0.0 ? 0u : (fy > a.cell_ymax ? a.ny - 1 : (uint32_t)fy);
   return ((uint32_t)(v >> 1) * a.nx + ix) * a.ny + iy;
 }
 
@@ -490,20 +526,21 @@ __device__ __forceinline__ T sel3(int i, T x0, T x1, T x2) {
   return i == 0 ? x0 : (i == 1 ? x1 : x2);
 }
 
-// Write one creation (full record) of type d at slot s of physical buffer b.
+// Write creation slot i (full record) of type d at slot s of physical buffer b;
+// n is the counter of the step that made it.
 template <int MAP, class P, bool INSTR>
 __device__ __forceinline__ void write_creation(const KArgs& a, int d, int b, uint64_t s, bool on,
                                                const Track<typename P::R>& t, const Creations<typename P::R>& cr,
-                                               int i) {
+                                               int i, uint32_t n) {
   using R = typename P::R;
   const auto A = make_acc<MAP, P, INSTR>(a, d, b, on);
-  const int ds = sel3<int>(i, cr.dsel[0], cr.dsel[1], cr.dsel[2]);
+  const int ds = cr.dsel(i);
   R dir[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) dir[k] = ds == 0 ? t.dir[k] : (ds == 1 ? cr.d[k] : -cr.d[k]);
-  const bool ps = sel3<int>(i, cr.psel[0], cr.psel[1], cr.psel[2]) != 0;
+  const uint64_t parent = creation_parent(cr, i, t.seed, t.id, n);
   store_full<MAP, P, INSTR>(A, s, t.pos, dir, sel3(i, cr.E[0], cr.E[1], cr.E[2]), (R)-1,
-                            sel3(i, cr.id[0], cr.id[1], cr.id[2]), ps ? cr.vid : t.id, t.seed, 0u, t.vol, t.event);
+                            creation_id(cr, i, t.seed, parent, n), parent, t.seed, 0u, t.vol, t.event);
 }
 
 // ---------------------------------------------------------------------------
@@ -565,6 +602,7 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
     Track<R> t;
     Creations<R> cr;
     cr.n = 0;
+    cr.meta = 0;
     Deposits dep{0.0, 0.0, 0.0, 0.0, {0.0, 0.0}};
     bool surv = false;
     int v0 = 0, lim_code = 0;
@@ -580,7 +618,7 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
       const unsigned long long vm = __ballot(valid);
       if (vm) {
         const int first = __ffsll((long long)vm) - 1;
-        const int ref = __shfl(lim_code, first, 64);
+        const int ref = __builtin_amdgcn_readlane(lim_code, first);
         const unsigned long long dm = __ballot(valid && lim_code != ref);
         const unsigned long long sm = __ballot(valid && surv);
         if (lane == first) {
@@ -599,7 +637,7 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
       for (int d = 0; d < 3; ++d) {
         uint32_t c_new = 0;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) c_new += (i < cr.n && cr.type[i] == d) ? 1u : 0u;
+        for (int i = 0; i < 3; ++i) c_new += (i < cr.n && cr.type(i) == d) ? 1u : 0u;
         cnt[d] = c_new + ((surv && D == d) ? 1u : 0u);
         if (SCHEME == SPARSE) {
           cnt[3 + d] = c_new;
@@ -608,6 +646,8 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
       }
     }
     const int ncr = cr.n;
+    // counter of this step: a surviving track leaves it with the next one
+    const uint32_t n_step = t.ctr - (surv ? 1u : 0u);
     uint32_t lex[NV];
     block_scan<NV>(cnt, lex, sh);
     lookback<NV>(a.desc[p], tile, sh, &c->overflow);
@@ -640,9 +680,9 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
         }
 #pragma unroll 1
         for (int i = 0; i < ncr; ++i) {  // one copy of the record store for every creation
-          const int d = sel3<int>(i, cr.type[0], cr.type[1], cr.type[2]);
+          const int d = cr.type(i);
           const unsigned long long pos = next_pos(d);
-          if (pos < a.C) write_creation<MAP, P, INSTR>(a, d, bn, pos, counting, t, cr, i);
+          if (pos < a.C) write_creation<MAP, P, INSTR>(a, d, bn, pos, counting, t, cr, i, n_step);
           else atomicOr(&c->overflow, 1ull);
         }
       } else {
@@ -660,7 +700,7 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
         }
 #pragma unroll 1
         for (int i = 0; i < ncr; ++i) {
-          const int d = sel3<int>(i, cr.type[0], cr.type[1], cr.type[2]);
+          const int d = cr.type(i);
           const unsigned long long pos = next_pos(d);
           const uint32_t r = d == 0 ? n0_ : (d == 1 ? n1_ : n2_);
           n0_ += d == 0 ? 1u : 0u;
@@ -669,7 +709,7 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
           const unsigned long long j = sh.tile_excl[(SCHEME == SPARSE ? 3 : 0) + d] + r;
           if (j < c->count[d] && pos < a.C) {
             const uint32_t s = a.ring[d][(c->head[d] + j) % a.C];
-            write_creation<MAP, P, INSTR>(a, d, 0, s, counting, t, cr, i);
+            write_creation<MAP, P, INSTR>(a, d, 0, s, counting, t, cr, i, n_step);
             a.list[d][1 - p][pos] = s;
           } else {
             atomicOr(&c->overflow, 1ull);
@@ -730,6 +770,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_inject(const KArgs a) {
     Track<R> t;
     Creations<R> cr;
     cr.n = 0;
+    cr.meta = 0;
     Deposits dep{0.0, 0.0, 0.0, 0.0, {0.0, 0.0}};
     int type = 0;
     bool keep = false;
@@ -775,7 +816,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_inject(const KArgs a) {
       for (int d = 0; d < 3; ++d) {
         uint32_t c_ = (keep && type == d) ? 1u : 0u;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) c_ += (i < cr.n && cr.type[i] == d) ? 1u : 0u;
+        for (int i = 0; i < 3; ++i) c_ += (i < cr.n && cr.type(i) == d) ? 1u : 0u;
         cnt[d] = c_;
       }
     }
@@ -792,7 +833,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_inject(const KArgs a) {
 #pragma unroll
       for (int o = 0; o < 3; ++o) {
         if (o >= nout) continue;
-        const int d = keep ? type : cr.type[o];
+        const int d = keep ? type : cr.type(o);
         const uint32_t r = d == 0 ? k0 : (d == 1 ? k1 : k2);
         k0 += d == 0 ? 1u : 0u;
         k1 += d == 1 ? 1u : 0u;
@@ -816,7 +857,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_inject(const KArgs a) {
           const auto A = make_acc<MAP, P, INSTR>(a, d, b, counting);
           store_full<MAP, P, INSTR>(A, s, t.pos, t.dir, t.E, t.nl, t.id, ~0ull, t.seed, 0u, t.vol, t.event);
         } else {
-          write_creation<MAP, P, INSTR>(a, d, b, s, counting, t, cr, o);
+          write_creation<MAP, P, INSTR>(a, d, b, s, counting, t, cr, o, 0u);
         }
       }
     }

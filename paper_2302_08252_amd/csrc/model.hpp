@@ -314,27 +314,42 @@ struct Track {
 template <class R>
 struct Creations {
   int n;
-  uint8_t type[3], dsel[3], psel[3];
+  // per slot s, bits [8s, 8s+7): type (2 bits), dsel (2), psel (1), k (2);
+  // bits [24, 26): k of the virtual positron
+  uint32_t meta;
   R E[3];
-  uint64_t id[3];
   R d[3];
-  uint64_t vid;
 
-  // Append one creation; slots are addressed with constant indices only so the
-  // arrays stay in registers.
-  AD_HD void push(int ty, int ds, int ps, R e, uint64_t i) {
+  AD_HD int type(int s) const { return (int)((meta >> (8 * s)) & 3u); }
+  AD_HD int dsel(int s) const { return (int)((meta >> (8 * s + 2)) & 3u); }
+  AD_HD int psel(int s) const { return (int)((meta >> (8 * s + 4)) & 1u); }
+  AD_HD uint32_t kid(int s) const { return (meta >> (8 * s + 5)) & 3u; }
+  AD_HD uint32_t vk() const { return (meta >> 24) & 3u; }
+
+  // Append one creation (type, direction select, parent select, energy, index k
+  // of the creation among its parent's creations at this step).  Slots are
+  // addressed with constant indices only so the arrays stay in registers.
+  AD_HD void push(int ty, int ds, int ps, R e, uint32_t k) {
+    meta |= (uint32_t)(ty | (ds << 2) | (ps << 4) | (int)(k << 5)) << (8 * n);
 #pragma unroll
-    for (int s = 0; s < 3; ++s) {  // value selects, no pointer selects
-      const bool here = n == s;
-      type[s] = here ? (uint8_t)ty : type[s];
-      dsel[s] = here ? (uint8_t)ds : dsel[s];
-      psel[s] = here ? (uint8_t)ps : psel[s];
-      E[s] = here ? e : E[s];
-      id[s] = here ? i : id[s];
-    }
+    for (int s = 0; s < 3; ++s) E[s] = n == s ? e : E[s];  // value selects, no pointer selects
     n += 1;
   }
 };
+
+// Ids of creation slot i of a step of track (seed, id) at counter n: a slot
+// whose parent is the stepping track has id child_id(seed, id, n, k); one whose
+// parent is a virtual positron (created below the cut and annihilated at once)
+// has parent vid = child_id(seed, id, n, vk) and id child_id(seed, vid, 0, k).
+// Recomputed where the record is written instead of being carried in registers.
+template <class R>
+AD_HD uint64_t creation_parent(const Creations<R>& cr, int i, uint32_t seed, uint64_t id, uint32_t n) {
+  return cr.psel(i) ? child_id(seed, id, n, cr.vk()) : id;
+}
+template <class R>
+AD_HD uint64_t creation_id(const Creations<R>& cr, int i, uint32_t seed, uint64_t parent, uint32_t n) {
+  return child_id(seed, parent, cr.psel(i) ? 0u : n, cr.kid(i));
+}
 
 // Deposits of one step, handed to the tally stage.
 struct Deposits {
@@ -369,29 +384,27 @@ AD_HD void annihilate(const Creator<P>& X0, int* kidx, int psel, Creations<typen
   out.d[0] = st * cp;
   out.d[1] = st * sp;
   out.d[2] = c;
-  const uint64_t id1 = child_id(X0.seed, X0.id, X0.n, (uint32_t)(*kidx)++);
-  out.push(GAMMA, 1, psel, Consts<R>::me, id1);
-  const uint64_t id2 = child_id(X0.seed, X0.id, X0.n, (uint32_t)(*kidx)++);
-  out.push(GAMMA, 2, psel, Consts<R>::me, id2);
+  out.push(GAMMA, 1, psel, Consts<R>::me, (uint32_t)(*kidx)++);
+  out.push(GAMMA, 2, psel, Consts<R>::me, (uint32_t)(*kidx)++);
 }
 
 template <class P>
 AD_HD void create(const Creator<P>& X, int* kidx, int type, typename P::R E, Creations<typename P::R>& out,
                   Deposits& dep) {
   using R = typename P::R;
-  const uint64_t id = child_id(X.seed, X.id, X.n, (uint32_t)(*kidx)++);
+  const uint32_t k = (uint32_t)(*kidx)++;
   const bool subcut = type == GAMMA ? (E < Consts<R>::cut_g) : (E < Consts<R>::cut_e);
   if (subcut) {
     dep.cut += (double)E;
     if (type == POSITRON) {
-      Creator<P> V{X.seed, id, 0u, 0};
+      Creator<P> V{X.seed, child_id(X.seed, X.id, X.n, k), 0u, 0};
       int k2 = 0;
-      out.vid = id;
+      out.meta |= k << 24;
       annihilate<P>(V, &k2, 1, out);
     }
     return;
   }
-  out.push(type, 0, 0, E, id);
+  out.push(type, 0, 0, E, k);
 }
 
 // Rotation taking z-hat to u, applied to (dx, dy, dz); no renormalisation.

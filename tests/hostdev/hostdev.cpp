@@ -35,6 +35,7 @@ static int step_one(int type, const TrackIO* in, int* surv, TrackIO out[4], int 
   t.event = in->event;
   Creations<R> cr;
   cr.n = 0;
+  cr.meta = 0;
   Deposits d{0.0, 0.0, 0.0, 0.0, {0.0, 0.0}};
   const bool s = type == GAMMA ? step_photon<P>(t, cr, d) : step_charged<P>(t, type, cr, d);
   int k = 0;
@@ -58,18 +59,18 @@ static int step_one(int type, const TrackIO* in, int* surv, TrackIO out[4], int 
     TrackIO& o = out[k];
     for (int j = 0; j < 3; ++j) {
       o.pos[j] = t.pos[j];
-      const R dd = cr.dsel[i] == 0 ? t.dir[j] : (cr.dsel[i] == 1 ? cr.d[j] : -cr.d[j]);
+      const R dd = cr.dsel(i) == 0 ? t.dir[j] : (cr.dsel(i) == 1 ? cr.d[j] : -cr.d[j]);
       o.dir[j] = (double)dd;
     }
     o.E = (double)cr.E[i];
     o.nl = -1.0;
-    o.id = cr.id[i];
-    o.parent = cr.psel[i] ? cr.vid : t.id;
+    o.parent = creation_parent(cr, i, t.seed, t.id, in->ctr);
+    o.id = creation_id(cr, i, t.seed, o.parent, in->ctr);
     o.seed = t.seed;
     o.ctr = 0;
     o.vol = t.vol;
     o.event = t.event;
-    out_type[k++] = cr.type[i];
+    out_type[k++] = cr.type(i);
   }
   *surv = s ? 1 : 0;
   dep[0] = d.cont;
