@@ -201,12 +201,14 @@ __device__ __forceinline__ unsigned long long widen3(uint32_t t) {
          ((unsigned long long)(t & 0x3FF00000u) << 12);
 }
 
-// Block-exclusive prefix per lane (lex) and block aggregate (agg, in LDS).
+// Block-exclusive prefix per lane (lex); every lane also receives the block
+// aggregate, lane v < NV of each wavefront the aggregate of value v (agg).
 // Per-lane counts are below 5 and a wavefront's totals below 2^10, so a
 // wavefront scans three counts per 32-bit word; sums over wavefronts (below
-// 2^13) use 16-bit fields.
+// 2^13) use 16-bit fields.  One barrier: the wave totals in LDS.
 template <int NV>
-__device__ __forceinline__ void block_scan(const uint32_t cnt[NV], uint32_t lex[NV], Scan<NV>& sh) {
+__device__ __forceinline__ void block_scan(const uint32_t cnt[NV], uint32_t lex[NV], unsigned long long& agg,
+                                           Scan<NV>& sh) {
   constexpr int W = Scan<NV>::W;
   const int lane = __lane_id(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   uint32_t x[W], inc[W];
@@ -220,6 +222,7 @@ __device__ __forceinline__ void block_scan(const uint32_t cnt[NV], uint32_t lex[
     if (lane == 63) sh.wave_tot[wave][w] = inc[w];
   }
   __syncthreads();
+  agg = 0;
 #pragma unroll
   for (int w = 0; w < W; ++w) {
     unsigned long long before = 0, all = 0;
@@ -233,10 +236,9 @@ __device__ __forceinline__ void block_scan(const uint32_t cnt[NV], uint32_t lex[
     for (int k = 0; k < 3; ++k)
       if (3 * w + k < NV) {
         lex[3 * w + k] = (uint32_t)((ex >> (16 * k)) & 0xFFFF);
-        if (threadIdx.x == 0) sh.tile_agg[3 * w + k] = (all >> (16 * k)) & 0xFFFF;
+        if (lane == 3 * w + k) agg = (all >> (16 * k)) & 0xFFFF;
       }
   }
-  __syncthreads();
 }
 
 // Decoupled look-back by wavefront 0: publishes the tile aggregate, gathers
@@ -248,19 +250,19 @@ __device__ __forceinline__ void block_scan(const uint32_t cnt[NV], uint32_t lex[
 constexpr unsigned kSpinLimit = 1u << 24;
 
 template <int NV>
-__device__ __forceinline__ void lookback(unsigned long long* desc, unsigned long long tile, Scan<NV>& sh,
-                                         unsigned long long* err) {
+__device__ __forceinline__ void lookback(unsigned long long* desc, unsigned long long tile, unsigned long long agg,
+                                         Scan<NV>& sh, unsigned long long* err) {
   if (threadIdx.x >= 64) return;
   const int lane = __lane_id();
+  if (lane < NV) sh.tile_agg[lane] = agg;
   if (tile == 0) {
     if (lane < NV) {
-      const unsigned long long a = sh.tile_agg[lane];
-      st_agent(&desc[lane], kStP | (a << 31) | a);
+      st_agent(&desc[lane], kStP | (agg << 31) | agg);
       sh.tile_excl[lane] = 0;
     }
     return;
   }
-  if (lane < NV) st_agent(&desc[tile * NV + lane], kStA | sh.tile_agg[lane]);
+  if (lane < NV) st_agent(&desc[tile * NV + lane], kStA | agg);
   unsigned long long acc[NV];
   long long base[NV];
   bool done[NV];
@@ -308,8 +310,7 @@ __device__ __forceinline__ void lookback(unsigned long long* desc, unsigned long
 #pragma unroll
     for (int v = 0; v < NV; ++v)
       if (v == lane) ex = acc[v];
-    const unsigned long long a = sh.tile_agg[lane];
-    st_agent(&desc[tile * NV + lane], kStP | (sat_add(ex, a) << 31) | a);
+    st_agent(&desc[tile * NV + lane], kStP | (sat_add(ex, agg) << 31) | agg);
     sh.tile_excl[lane] = ex;
   }
 }
@@ -645,12 +646,17 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
         }
       }
     }
+    // a dense survivor's record is copied whole: its parent id is read here so
+    // that the load overlaps the scan and the look-back
+    uint64_t parent = 0;
+    if (SCHEME == DENSE && valid && surv) parent = Acur.template ld<uint64_t>(slot, 9);
     const int ncr = cr.n;
     // counter of this step: a surviving track leaves it with the next one
     const uint32_t n_step = t.ctr - (surv ? 1u : 0u);
     uint32_t lex[NV];
-    block_scan<NV>(cnt, lex, sh);
-    lookback<NV>(a.desc[p], tile, sh, &c->overflow);
+    unsigned long long agg;
+    block_scan<NV>(cnt, lex, agg, sh);
+    lookback<NV>(a.desc[p], tile, agg, sh, &c->overflow);
     __syncthreads();
     if (tile == total - 1 && threadIdx.x < NV)
       c->tot[p][threadIdx.x] = sat_add(sh.tile_excl[threadIdx.x], sh.tile_agg[threadIdx.x]);
@@ -670,7 +676,6 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
         const int bn = 1 - (int)p;
         if (surv) {
           const unsigned long long pos = next_pos(D);
-          const uint64_t parent = Acur.template ld<uint64_t>(slot, 9);
           if (pos < a.C) {
             const auto An = make_acc<MAP, P, INSTR>(a, D, bn, counting);
             store_full<MAP, P, INSTR>(An, pos, t.pos, t.dir, t.E, t.nl, t.id, parent, t.seed, t.ctr, t.vol, t.event);
@@ -717,7 +722,8 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
         }
       }
     }
-    __syncthreads();  // LDS scan state is reused by the next tile
+    // Every read of this tile's LDS state is done; the next tile's ticket is
+    // published before the one barrier that separates the two tiles.
     if (threadIdx.x == 0) sh.ticket = my_next;
     __syncthreads();
   }
@@ -821,8 +827,9 @@ __global__ void __launch_bounds__(kMaxBlock) k_inject(const KArgs a) {
       }
     }
     uint32_t lex[NV];
-    block_scan<NV>(cnt, lex, sh);
-    lookback<NV>(a.idesc[q], tile, sh, &c->overflow);
+    unsigned long long agg;
+    block_scan<NV>(cnt, lex, agg, sh);
+    lookback<NV>(a.idesc[q], tile, agg, sh, &c->overflow);
     __syncthreads();
     if (tile == total - 1 && threadIdx.x < NV)
       c->inj_tot[threadIdx.x] = sat_add(sh.tile_excl[threadIdx.x], sh.tile_agg[threadIdx.x]);
