@@ -202,12 +202,12 @@ def batched_section(ad, torch, np, workloads, args):
     kappa = kappa_cfg1()
     C = 1 << 24
     cands = [(1, 0, 1), (1, 1, 1), (1, 2, 16), (1, 2, 64), (1, 2, 256)]
-    sample = wl.primaries[wl.primaries["event"] < 4]  # ~2600 primaries: peak ~1e6 photons < 2^22
-    layout, launch, _ = ad.adept_autotune_layout(ad.MIXED, 1 << 22, cands, wl.seeds[:4], sample)
+    sample = wl.primaries[wl.primaries["event"] < 16]  # ~16k primaries: peak ~5e6 photons < 2^23
+    layout, launch, _ = ad.adept_autotune_layout(ad.MIXED, 1 << 23, cands, wl.seeds[:16], sample)
     out = {"workload": wl.description, "capacity_per_type": C, "admission": {"alpha": 0.8, "kappa_per_GeV": kappa},
            "autotuned": {"layout": {"scheme": "dense" if layout[0] else "sparse",
                                     "mapping": ["AoS", "SoA", "AoSoA"][layout[1]], "lanes": layout[2]},
-                         "launch": launch, "tuning_sample": "events 0-3, capacity 2^22"}}
+                         "launch": launch, "tuning_sample": "events 0-15, capacity 2^23"}}
     sim = ad.Sim(layout[0], layout[1], ad.MIXED, C, layout[2], seeds=wl.seeds, admission=(0.8, kappa), launch=launch)
     dt, it, st = run_once(ad, torch, sim, wl.primaries)
     ts = sum(st["track_steps"])
