@@ -181,9 +181,11 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 constexpr unsigned long long kSat = (1ull << 31) - 1;
 constexpr unsigned long long kStA = 1ull << 62, kStP = 2ull << 62;
 
-template <int NV>
+// LDS state of the ordered compaction: NS values scanned per lane (NV values
+// per track times the tracks a lane holds), NV values per tile.
+template <int NS, int NV = NS>
 struct Scan {
-  static constexpr int W = (NV + 2) / 3;  // 32-bit words of three 10-bit fields
+  static constexpr int W = (NS + 2) / 3;  // 32-bit words of three 10-bit fields
   uint32_t wave_tot[kMaxWaves][W];
   unsigned long long tile_excl[NV];
   unsigned long long tile_agg[NV];
@@ -201,15 +203,15 @@ __device__ __forceinline__ unsigned long long widen3(uint32_t t) {
          ((unsigned long long)(t & 0x3FF00000u) << 12);
 }
 
-// Block-exclusive prefix per lane (lex); every lane also receives the block
-// aggregate, lane v < NV of each wavefront the aggregate of value v (agg).
-// Per-lane counts are below 5 and a wavefront's totals below 2^10, so a
+// Block-exclusive prefix per lane (lex) and the block aggregates of all NV
+// values, packed three per 64-bit word in 16-bit fields (aggw; the same in every
+// lane).  Per-lane counts are below 5 and a wavefront's totals below 2^10, so a
 // wavefront scans three counts per 32-bit word; sums over wavefronts (below
 // 2^13) use 16-bit fields.  One barrier: the wave totals in LDS.
-template <int NV>
-__device__ __forceinline__ void block_scan(const uint32_t cnt[NV], uint32_t lex[NV], unsigned long long& agg,
-                                           Scan<NV>& sh) {
-  constexpr int W = Scan<NV>::W;
+template <int NV, class S>
+__device__ __forceinline__ void block_scan(const uint32_t cnt[NV], uint32_t lex[NV],
+                                           unsigned long long aggw[(NV + 2) / 3], S& sh) {
+  constexpr int W = (NV + 2) / 3;
   const int lane = __lane_id(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   uint32_t x[W], inc[W];
 #pragma unroll
@@ -222,7 +224,6 @@ __device__ __forceinline__ void block_scan(const uint32_t cnt[NV], uint32_t lex[
     if (lane == 63) sh.wave_tot[wave][w] = inc[w];
   }
   __syncthreads();
-  agg = 0;
 #pragma unroll
   for (int w = 0; w < W; ++w) {
     unsigned long long before = 0, all = 0;
@@ -234,11 +235,15 @@ __device__ __forceinline__ void block_scan(const uint32_t cnt[NV], uint32_t lex[
     const unsigned long long ex = before + widen3(inc[w] - x[w]);
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-      if (3 * w + k < NV) {
-        lex[3 * w + k] = (uint32_t)((ex >> (16 * k)) & 0xFFFF);
-        if (lane == 3 * w + k) agg = (all >> (16 * k)) & 0xFFFF;
-      }
+      if (3 * w + k < NV) lex[3 * w + k] = (uint32_t)((ex >> (16 * k)) & 0xFFFF);
+    aggw[w] = all;
   }
+}
+
+// Value v of packed block aggregates.
+template <int NV>
+__device__ __forceinline__ uint32_t agg_value(const unsigned long long aggw[(NV + 2) / 3], int v) {
+  return (uint32_t)((aggw[v / 3] >> (16 * (v % 3))) & 0xFFFF);
 }
 
 // Decoupled look-back by wavefront 0: publishes the tile aggregate, gathers
@@ -249,9 +254,9 @@ __device__ __forceinline__ void block_scan(const uint32_t cnt[NV], uint32_t lex[
 // always reaches its exit.
 constexpr unsigned kSpinLimit = 1u << 24;
 
-template <int NV>
+template <int NV, class S>
 __device__ __forceinline__ void lookback(unsigned long long* desc, unsigned long long tile, unsigned long long agg,
-                                         Scan<NV>& sh, unsigned long long* err) {
+                                         S& sh, unsigned long long* err) {
   if (threadIdx.x >= 64) return;
   const int lane = __lane_id();
   if (lane < NV) sh.tile_agg[lane] = agg;
@@ -539,27 +544,98 @@ __device__ __forceinline__ void write_creation(const KArgs& a, int d, int b, uin
   R dir[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) dir[k] = ds == 0 ? t.dir[k] : (ds == 1 ? cr.d[k] : -cr.d[k]);
-  const uint64_t parent = creation_parent(cr, i, t.seed, t.id, n);
+  const uint64_t parent = creation_parent<P::philox_unroll>(cr, i, t.seed, t.id, n);
   store_full<MAP, P, INSTR>(A, s, t.pos, dir, sel3(i, cr.E[0], cr.E[1], cr.E[2]), (R)-1,
-                            creation_id(cr, i, t.seed, parent, n), parent, t.seed, 0u, t.vol, t.event);
+                            creation_id<P::philox_unroll>(cr, i, t.seed, parent, n), parent, t.seed, 0u, t.vol, t.event);
 }
 
 // ---------------------------------------------------------------------------
-// The fused step kernel.
+// Outputs of a stepped track kept in LDS while the lane steps its next track
+// (field-major: consecutive lanes touch consecutive words).  `aux` holds the
+// parent id of a dense survivor or the slot of a sparse source.
+// ---------------------------------------------------------------------------
+template <class R, bool ON>
+struct Park {};
+template <class R>
+struct Park<R, true> {
+  double pos[3][kMaxBlock];
+  uint64_t id[kMaxBlock], aux[kMaxBlock];
+  R dir[3][kMaxBlock], E[kMaxBlock], nl[kMaxBlock];
+  R cE[3][kMaxBlock], cd[3][kMaxBlock];
+  uint32_t seed[kMaxBlock], ctr[kMaxBlock], vol[kMaxBlock], event[kMaxBlock], meta[kMaxBlock];
+  uint32_t flags[kMaxBlock];  // creations (2 bits), survived (bit 2), valid (bit 3)
+};
+
+template <class R>
+__device__ __forceinline__ void park(Park<R, true>& k, int i, const Track<R>& t, const Creations<R>& cr, bool surv,
+                                     bool valid, uint64_t aux) {
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    k.pos[j][i] = t.pos[j];
+    k.dir[j][i] = t.dir[j];
+    k.cE[j][i] = cr.E[j];
+    k.cd[j][i] = cr.d[j];
+  }
+  k.E[i] = t.E;
+  k.nl[i] = t.nl;
+  k.id[i] = t.id;
+  k.aux[i] = aux;
+  k.seed[i] = t.seed;
+  k.ctr[i] = t.ctr;
+  k.vol[i] = (uint32_t)t.vol;
+  k.event[i] = t.event;
+  k.meta[i] = cr.meta;
+  k.flags[i] = (uint32_t)cr.n | (surv ? 4u : 0u) | (valid ? 8u : 0u);
+}
+
+template <class R>
+__device__ __forceinline__ void unpark(const Park<R, true>& k, int i, Track<R>& t, Creations<R>& cr, bool& surv,
+                                       bool& valid, uint64_t& aux) {
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    t.pos[j] = k.pos[j][i];
+    t.dir[j] = k.dir[j][i];
+    cr.E[j] = k.cE[j][i];
+    cr.d[j] = k.cd[j][i];
+  }
+  t.E = k.E[i];
+  t.nl = k.nl[i];
+  t.id = k.id[i];
+  aux = k.aux[i];
+  t.seed = k.seed[i];
+  t.ctr = k.ctr[i];
+  t.vol = (int32_t)k.vol[i];
+  t.event = k.event[i];
+  cr.meta = k.meta[i];
+  const uint32_t f = k.flags[i];
+  cr.n = (int)(f & 3u);
+  surv = (f & 4u) != 0;
+  valid = (f & 8u) != 0;
+}
+
+// ---------------------------------------------------------------------------
+// The fused step kernel.  A tile is TPT * blockDim.x consecutive tracks of one
+// type; lane l steps tracks l, l + blockDim.x, ...  The outputs of all but the
+// last are parked in LDS, so the scan, the look-back and the barriers of a tile
+// are paid once for TPT tracks per lane.  Canonical order within a tile: the
+// sources in index order, i.e. the first track of every lane, then the second.
 // ---------------------------------------------------------------------------
 template <int SCHEME, int MAP, class P, bool INSTR, int LB>
 __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
   using R = typename P::R;
   constexpr int NV = SCHEME == DENSE ? 3 : 9;  // next[3] (+ new[3], kill[3])
-  __shared__ Scan<NV> sh;
+  constexpr int TPT = P::tracks_per_lane(LB);
+  constexpr int NS = NV * TPT;
+  __shared__ Scan<NS, NV> sh;
+  __shared__ Park<R, (TPT > 1)> pk;
   __shared__ TallyLDS tl;
   __shared__ TallyCache tc;
   __shared__ StatLDS ss;
   Ctrl* c = a.ctrl;
   const uint32_t p = c->parity;
   const unsigned long long n0 = c->n[p][0], n1 = c->n[p][1], n2 = c->n[p][2];
-  const unsigned long long T = blockDim.x;
-  const unsigned long long t0 = ceil_div(n0, T), t1 = ceil_div(n1, T), t2 = ceil_div(n2, T);
+  const unsigned long long T = blockDim.x, TT = T * TPT;
+  const unsigned long long t0 = ceil_div(n0, TT), t1 = ceil_div(n1, TT), t2 = ceil_div(n2, TT);
   const unsigned long long total = t0 + t1 + t2;
   const bool counting = INSTR && a.instr_on && c->iter < a.instr_last;
   const bool lds_tally = a.n_events == 1 && !a.cells;
@@ -595,76 +671,107 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
     if (tile < t0) { D = ELECTRON; lt = tile; nD = n0; }
     else if (tile < t0 + t1) { D = POSITRON; lt = tile - t0; nD = n1; }
     else { D = GAMMA; lt = tile - t0 - t1; nD = n2; }
-    const unsigned long long idx = lt * T + threadIdx.x;
-    const bool valid = idx < nD;
     const int bcur = SCHEME == DENSE ? (int)p : 0;
     const auto Acur = make_acc<MAP, P, INSTR>(a, D, bcur, counting);
-    uint32_t slot = 0;
+    uint32_t cnt[NS];
+#pragma unroll
+    for (int v = 0; v < NS; ++v) cnt[v] = 0;
+    // state of the lane's last track of the tile (the earlier ones are parked)
     Track<R> t;
     Creations<R> cr;
-    cr.n = 0;
-    cr.meta = 0;
-    Deposits dep{0.0, 0.0, 0.0, 0.0, {0.0, 0.0}};
-    bool surv = false;
-    int v0 = 0, lim_code = 0;
-    if (valid) {
-      slot = SCHEME == DENSE ? (uint32_t)idx : a.list[D][p][idx];
-      load_track<MAP, P, INSTR>(Acur, slot, t);
-      v0 = t.vol;
-      surv = D == GAMMA ? step_photon<P>(t, cr, dep) : step_charged<P>(t, D, cr, dep);
-      lim_code = (surv ? 1 : 0) | (cr.n << 1);
-      book(a, lds_tally ? &tl : nullptr, lds_tally ? nullptr : &tc, t.event, v0, dep, t.pos);
-    }
-    {  // divergence diagnostic: lanes of a wavefront that disagree on the outcome
-      const unsigned long long vm = __ballot(valid);
-      if (vm) {
-        const int first = __ffsll((long long)vm) - 1;
-        const int ref = __builtin_amdgcn_readlane(lim_code, first);
-        const unsigned long long dm = __ballot(valid && lim_code != ref);
-        const unsigned long long sm = __ballot(valid && surv);
-        if (lane == first) {
-          atomicAdd(&ss.waves, 1ull);
-          if (dm) atomicAdd(&ss.waves_div, 1ull);
-          if (sm) atomicAdd(&ss.surv[D], (unsigned long long)__popcll(sm));
+    bool surv = false, valid = false;
+    uint64_t aux = 0;  // dense: parent id of a survivor; sparse: slot
+#pragma unroll
+    for (int u = 0; u < TPT; ++u) {
+      const unsigned long long idx = lt * TT + (unsigned long long)u * T + threadIdx.x;
+      valid = idx < nD;
+      cr.n = 0;
+      cr.meta = 0;
+      surv = false;
+      aux = 0;
+      Deposits dep{0.0, 0.0, 0.0, 0.0, {0.0, 0.0}};
+      int lim_code = 0;
+      uint32_t slot = 0;
+      if (valid) {
+        slot = SCHEME == DENSE ? (uint32_t)idx : a.list[D][p][idx];
+        load_track<MAP, P, INSTR>(Acur, slot, t);
+        const int v0 = t.vol;
+        surv = D == GAMMA ? step_photon<P>(t, cr, dep) : step_charged<P>(t, D, cr, dep);
+        lim_code = (surv ? 1 : 0) | (cr.n << 1);
+        book(a, lds_tally ? &tl : nullptr, lds_tally ? nullptr : &tc, t.event, v0, dep, t.pos);
+      }
+      {  // divergence diagnostic: lanes of a wavefront that disagree on the outcome
+        const unsigned long long vm = __ballot(valid);
+        if (vm) {
+          const int first = __ffsll((long long)vm) - 1;
+          const int ref = __builtin_amdgcn_readlane(lim_code, first);
+          const unsigned long long dm = __ballot(valid && lim_code != ref);
+          const unsigned long long sm = __ballot(valid && surv);
+          if (lane == first) {
+            atomicAdd(&ss.waves, 1ull);
+            if (dm) atomicAdd(&ss.waves_div, 1ull);
+            if (sm) atomicAdd(&ss.surv[D], (unsigned long long)__popcll(sm));
+          }
         }
       }
-    }
-    // output counts of this lane (constant indices only: the arrays stay in registers)
-    uint32_t cnt[NV];
+      // output counts of this track (constant indices only: the arrays stay in registers)
+      if (valid) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) cnt[v] = 0;
-    if (valid) {
+        for (int d = 0; d < 3; ++d) {
+          uint32_t c_new = 0;
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        uint32_t c_new = 0;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) c_new += (i < cr.n && cr.type(i) == d) ? 1u : 0u;
-        cnt[d] = c_new + ((surv && D == d) ? 1u : 0u);
-        if (SCHEME == SPARSE) {
-          cnt[3 + d] = c_new;
-          cnt[6 + d] = (!surv && D == d) ? 1u : 0u;
+          for (int i = 0; i < 3; ++i) c_new += (i < cr.n && cr.type(i) == d) ? 1u : 0u;
+          cnt[u * NV + d] = c_new + ((surv && D == d) ? 1u : 0u);
+          if (SCHEME == SPARSE) {
+            cnt[u * NV + 3 + d] = c_new;
+            cnt[u * NV + 6 + d] = (!surv && D == d) ? 1u : 0u;
+          }
         }
       }
+      // a dense survivor's record is copied whole: its parent id is read here so
+      // that the load overlaps the rest of the tile's work
+      if (SCHEME == DENSE) {
+        if (valid && surv) aux = Acur.template ld<uint64_t>(slot, 9);
+      } else {
+        aux = slot;
+      }
+      if constexpr (TPT > 1) {
+        if (u < TPT - 1) park(pk, threadIdx.x, t, cr, surv, valid, aux);
+      }
     }
-    // a dense survivor's record is copied whole: its parent id is read here so
-    // that the load overlaps the scan and the look-back
-    uint64_t parent = 0;
-    if (SCHEME == DENSE && valid && surv) parent = Acur.template ld<uint64_t>(slot, 9);
-    const int ncr = cr.n;
-    // counter of this step: a surviving track leaves it with the next one
-    const uint32_t n_step = t.ctr - (surv ? 1u : 0u);
-    uint32_t lex[NV];
-    unsigned long long agg;
-    block_scan<NV>(cnt, lex, agg, sh);
+    uint32_t lex[NS];
+    unsigned long long aggw[(NS + 2) / 3];
+    block_scan<NS>(cnt, lex, aggw, sh);
+    unsigned long long agg = 0;  // lane v < NV: the tile aggregate of value v
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      unsigned long long sum = 0;
+#pragma unroll
+      for (int u = 0; u < TPT; ++u) sum += agg_value<NS>(aggw, u * NV + v);
+      if (lane == v) agg = sum;
+    }
     lookback<NV>(a.desc[p], tile, agg, sh, &c->overflow);
     __syncthreads();
     if (tile == total - 1 && threadIdx.x < NV)
       c->tot[p][threadIdx.x] = sat_add(sh.tile_excl[threadIdx.x], sh.tile_agg[threadIdx.x]);
     if (threadIdx.x == 0)
       my_next = __hip_atomic_fetch_add(&c->ticket[p], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (valid) {
-      // running position of this lane's next output of each type (next list / dense index)
-      uint32_t k0 = lex[0], k1 = lex[1], k2 = lex[2];
+
+    // Writes of one track u of this lane: survivor, kill, creations.
+    auto emit = [&](int u, const Track<R>& t, const Creations<R>& cr, bool surv, uint64_t aux) {
+      // tile-local exclusive prefix of value v for this track: the outputs of the
+      // lane's earlier tracks' sub-tiles come first
+      auto base = [&](int v) -> uint32_t {
+        uint32_t b = 0;
+#pragma unroll
+        for (int w = 0; w < TPT; ++w)
+          if (w < u) b += agg_value<NS>(aggw, w * NV + v);
+        return b + lex[u * NV + v];
+      };
+      const uint32_t n_step = t.ctr - (surv ? 1u : 0u);  // a survivor leaves with the next counter
+      const int ncr = cr.n;
+      // running position of this track's next output of each type (next list / dense index)
+      uint32_t k0 = base(0), k1 = base(1), k2 = base(2);
       auto next_pos = [&](int d) -> unsigned long long {
         const uint32_t r = d == 0 ? k0 : (d == 1 ? k1 : k2);
         k0 += d == 0 ? 1u : 0u;
@@ -678,7 +785,7 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
           const unsigned long long pos = next_pos(D);
           if (pos < a.C) {
             const auto An = make_acc<MAP, P, INSTR>(a, D, bn, counting);
-            store_full<MAP, P, INSTR>(An, pos, t.pos, t.dir, t.E, t.nl, t.id, parent, t.seed, t.ctr, t.vol, t.event);
+            store_full<MAP, P, INSTR>(An, pos, t.pos, t.dir, t.E, t.nl, t.id, aux, t.seed, t.ctr, t.vol, t.event);
           } else {
             atomicOr(&c->overflow, 1ull);
           }
@@ -691,15 +798,16 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
           else atomicOr(&c->overflow, 1ull);
         }
       } else {
-        uint32_t n0_ = lex[SCHEME == SPARSE ? 3 : 0], n1_ = lex[SCHEME == SPARSE ? 4 : 1],
-                 n2_ = lex[SCHEME == SPARSE ? 5 : 2];
+        const uint32_t slot = (uint32_t)aux;
+        uint32_t m0 = base(SCHEME == SPARSE ? 3 : 0), m1 = base(SCHEME == SPARSE ? 4 : 1),
+                 m2 = base(SCHEME == SPARSE ? 5 : 2);
         if (surv) {
           const unsigned long long pos = next_pos(D);
           store_inplace<MAP, P, INSTR>(Acur, slot, t, D != GAMMA);
           if (pos < a.C) a.list[D][1 - p][pos] = slot;
         } else {
-          const uint32_t lk = D == 0 ? lex[SCHEME == SPARSE ? 6 : 0]
-                                     : (D == 1 ? lex[SCHEME == SPARSE ? 7 : 0] : lex[SCHEME == SPARSE ? 8 : 0]);
+          const uint32_t lk = D == 0 ? base(SCHEME == SPARSE ? 6 : 0)
+                                     : (D == 1 ? base(SCHEME == SPARSE ? 7 : 0) : base(SCHEME == SPARSE ? 8 : 0));
           const unsigned long long f = sh.tile_excl[6 % NV + (SCHEME == SPARSE ? D : 0)] + lk;
           a.ring[D][(c->head[D] + c->count[D] + f) % a.C] = slot;
         }
@@ -707,10 +815,10 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
         for (int i = 0; i < ncr; ++i) {
           const int d = cr.type(i);
           const unsigned long long pos = next_pos(d);
-          const uint32_t r = d == 0 ? n0_ : (d == 1 ? n1_ : n2_);
-          n0_ += d == 0 ? 1u : 0u;
-          n1_ += d == 1 ? 1u : 0u;
-          n2_ += d == 2 ? 1u : 0u;
+          const uint32_t r = d == 0 ? m0 : (d == 1 ? m1 : m2);
+          m0 += d == 0 ? 1u : 0u;
+          m1 += d == 1 ? 1u : 0u;
+          m2 += d == 2 ? 1u : 0u;
           const unsigned long long j = sh.tile_excl[(SCHEME == SPARSE ? 3 : 0) + d] + r;
           if (j < c->count[d] && pos < a.C) {
             const uint32_t s = a.ring[d][(c->head[d] + j) % a.C];
@@ -720,6 +828,14 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
             atomicOr(&c->overflow, 1ull);
           }
         }
+      }
+    };
+    if (valid) emit(TPT - 1, t, cr, surv, aux);
+    if constexpr (TPT > 1) {
+#pragma unroll
+      for (int u = 0; u < TPT - 1; ++u) {
+        unpark(pk, threadIdx.x, t, cr, surv, valid, aux);
+        if (valid) emit(u, t, cr, surv, aux);
       }
     }
     // Every read of this tile's LDS state is done; the next tile's ticket is
@@ -827,8 +943,12 @@ __global__ void __launch_bounds__(kMaxBlock) k_inject(const KArgs a) {
       }
     }
     uint32_t lex[NV];
-    unsigned long long agg;
-    block_scan<NV>(cnt, lex, agg, sh);
+    unsigned long long aggw[1];
+    block_scan<NV>(cnt, lex, aggw, sh);
+    unsigned long long agg = 0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      if (__lane_id() == v) agg = agg_value<NV>(aggw, v);
     lookback<NV>(a.idesc[q], tile, agg, sh, &c->overflow);
     __syncthreads();
     if (tile == total - 1 && threadIdx.x < NV)

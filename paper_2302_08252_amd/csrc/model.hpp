@@ -35,8 +35,13 @@ struct U4 {
   uint32_t x, y, z, w;
 };
 
+// U: rounds per loop iteration (a divisor of 10), a tuning choice of the
+// precision policy.  Fully unrolled, the round keys of each inlined call fold
+// into distinct constants that crowd the scalar registers; a short loop keeps
+// two of them.  The result does not depend on U.
+template <int U = 10>
 AD_HD U4 philox(U4 c, uint32_t k0, uint32_t k1) {
-#pragma unroll
+#pragma unroll U
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
@@ -49,14 +54,16 @@ AD_HD U4 philox(U4 c, uint32_t k0, uint32_t k1) {
 }
 
 // Block j of the stream of track (seed, id) at its own step n.
+template <int U = 10>
 AD_HD U4 track_block(uint32_t seed, uint64_t id, uint32_t n, uint32_t j) {
-  return philox(U4{n, j, (uint32_t)(id >> 32), 0u}, seed, (uint32_t)id);
+  return philox<U>(U4{n, j, (uint32_t)(id >> 32), 0u}, seed, (uint32_t)id);
 }
 
 // The k-th track created by (seed, id) at its step n: top bit set, the rest from
 // the first two words of block 2 + k.
+template <int U = 10>
 AD_HD uint64_t child_id(uint32_t seed, uint64_t id, uint32_t n, uint32_t k) {
-  const U4 r = track_block(seed, id, n, 2u + k);
+  const U4 r = track_block<U>(seed, id, n, 2u + k);
   return (1ull << 63) | ((uint64_t)(r.x & 0x7FFFFFFFu) << 32) | (uint64_t)r.y;
 }
 
@@ -266,11 +273,17 @@ AD_HD int cross(double p[3], const double d[3], int v, int axis) {
 struct PolicyF64 {
   using R = double;  // stepping / sampling / angle type
   static constexpr bool mixed = false;
+  static constexpr int philox_unroll = 5;  // measured fastest for this policy
+  // tracks a lane of the step kernel holds per tile (the parked outputs of the
+  // earlier ones take LDS: the binary64 records do not fit twice)
+  AD_HD static constexpr int tracks_per_lane(int block) { return 1; }
   AD_HD static R uni(uint32_t r) { return u01(r); }
 };
 struct PolicyMixed {
   using R = float;
   static constexpr bool mixed = true;
+  static constexpr int philox_unroll = 10;
+  AD_HD static constexpr int tracks_per_lane(int block) { return block >= 1024 ? 2 : 1; }
   AD_HD static R uni(uint32_t r) { return u01f(r); }
 };
 
@@ -342,13 +355,13 @@ struct Creations {
 // parent is a virtual positron (created below the cut and annihilated at once)
 // has parent vid = child_id(seed, id, n, vk) and id child_id(seed, vid, 0, k).
 // Recomputed where the record is written instead of being carried in registers.
-template <class R>
+template <int U = 10, class R>
 AD_HD uint64_t creation_parent(const Creations<R>& cr, int i, uint32_t seed, uint64_t id, uint32_t n) {
-  return cr.psel(i) ? child_id(seed, id, n, cr.vk()) : id;
+  return cr.psel(i) ? child_id<U>(seed, id, n, cr.vk()) : id;
 }
-template <class R>
+template <int U = 10, class R>
 AD_HD uint64_t creation_id(const Creations<R>& cr, int i, uint32_t seed, uint64_t parent, uint32_t n) {
-  return child_id(seed, parent, cr.psel(i) ? 0u : n, cr.kid(i));
+  return child_id<U>(seed, parent, cr.psel(i) ? 0u : n, cr.kid(i));
 }
 
 // Deposits of one step, handed to the tally stage.
@@ -375,7 +388,7 @@ template <class P>
 AD_HD void annihilate(const Creator<P>& X0, int* kidx, int psel, Creations<typename P::R>& out) {
   using R = typename P::R;
   using F = Fmt<R>;
-  const U4 b = track_block(X0.seed, X0.id, X0.n, 1u);
+  const U4 b = track_block<P::philox_unroll>(X0.seed, X0.id, X0.n, 1u);
   const R c = (R)2 * P::uni(b.y) - (R)1;
   const R st = F::sqrt_(rmax((R)0, (R)1 - c * c));
   const R ph = ((R)2 * F::pi) * P::uni(b.z);
@@ -397,7 +410,7 @@ AD_HD void create(const Creator<P>& X, int* kidx, int type, typename P::R E, Cre
   if (subcut) {
     dep.cut += (double)E;
     if (type == POSITRON) {
-      Creator<P> V{X.seed, child_id(X.seed, X.id, X.n, k), 0u, 0};
+      Creator<P> V{X.seed, child_id<P::philox_unroll>(X.seed, X.id, X.n, k), 0u, 0};
       int k2 = 0;
       out.meta |= k << 24;
       annihilate<P>(V, &k2, 1, out);
@@ -431,7 +444,7 @@ AD_HD bool step_charged(Track<typename P::R>& t, int type, Creations<typename P:
   using F = Fmt<R>;
   using C = Consts<R>;
   const uint32_t n = t.ctr;
-  const U4 a = track_block(t.seed, t.id, n, 0u);  // block 1 is drawn only where it is used
+  const U4 a = track_block<P::philox_unroll>(t.seed, t.id, n, 0u);  // block 1 is drawn only where it is used
   const Creator<P> X{t.seed, t.id, n, 0};
   int kidx = 0;
   const int v = t.vol, m = v & 1;
@@ -497,7 +510,7 @@ AD_HD bool step_charged(Track<typename P::R>& t, int type, Creations<typename P:
     const R E2 = E1 - k;
     k = E1 - E2;
     create<P>(X, &kidx, GAMMA, k, out, dep);
-    const U4 b = track_block(t.seed, t.id, n, 1u);
+    const U4 b = track_block<P::philox_unroll>(t.seed, t.id, n, 1u);
     nl = -plog<R>(P::uni(b.x));
     E = E2;
     if (E2 < C::cut_e) {
@@ -527,7 +540,7 @@ AD_HD bool step_photon(Track<typename P::R>& t, Creations<typename P::R>& out, D
   R nl = t.nl;
   // Random words are drawn only when used: a geometry-limited step of a photon
   // whose interaction length is already sampled needs none.
-  if (nl < (R)0) nl = -plog<R>(P::uni(track_block(t.seed, t.id, n, 0u).x));
+  if (nl < (R)0) nl = -plog<R>(P::uni(track_block<P::philox_unroll>(t.seed, t.id, n, 0u).x));
   const bool pair = E > C::pairth;
   const R lam = pair ? C::lpair(m) : C::lcomp(m);
   const R s_phys = nl * lam;
@@ -545,7 +558,7 @@ AD_HD bool step_photon(Track<typename P::R>& t, Creations<typename P::R>& out, D
     return false;
   }
   t.vol = v1;
-  const uint32_t a3 = lim == LIM_PHYS ? track_block(t.seed, t.id, n, 0u).w : 0u;
+  const uint32_t a3 = lim == LIM_PHYS ? track_block<P::philox_unroll>(t.seed, t.id, n, 0u).w : 0u;
   if (lim == LIM_PHYS && pair) {
     R T, r;
     two_sum<R>(E, -C::pairth, &T, &r);
@@ -559,7 +572,7 @@ AD_HD bool step_photon(Track<typename P::R>& t, Creations<typename P::R>& out, D
   }
   R Enew = E;
   if (lim == LIM_PHYS) {
-    const U4 b = track_block(t.seed, t.id, n, 1u);
+    const U4 b = track_block<P::philox_unroll>(t.seed, t.id, n, 1u);
     R T = P::uni(a3) * E;
     const R Ep = E - T;
     T = E - Ep;
