@@ -925,7 +925,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_inject(const KArgs a) {
         if (type == POSITRON) {
           const Creator<P> X{t.seed, t.id, 0u, 0};
           int kidx = 0;
-          annihilate<P>(X, &kidx, 0, cr);
+          annihilate<P>(track_block<P::philox_unroll>(X.seed, X.id, X.n, 1u), X, &kidx, 0, cr);
         }
         book(a, nullptr, nullptr, ev, t.vol, dep, t.pos);
       } else {

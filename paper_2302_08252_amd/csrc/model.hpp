@@ -384,11 +384,11 @@ struct Creator {
   int k;
 };
 
+// Annihilation of positron X0 at rest; b is block 1 of X0's stream.
 template <class P>
-AD_HD void annihilate(const Creator<P>& X0, int* kidx, int psel, Creations<typename P::R>& out) {
+AD_HD void annihilate(const U4& b, const Creator<P>& X0, int* kidx, int psel, Creations<typename P::R>& out) {
   using R = typename P::R;
   using F = Fmt<R>;
-  const U4 b = track_block<P::philox_unroll>(X0.seed, X0.id, X0.n, 1u);
   const R c = (R)2 * P::uni(b.y) - (R)1;
   const R st = F::sqrt_(rmax((R)0, (R)1 - c * c));
   const R ph = ((R)2 * F::pi) * P::uni(b.z);
@@ -413,7 +413,7 @@ AD_HD void create(const Creator<P>& X, int* kidx, int type, typename P::R E, Cre
       Creator<P> V{X.seed, child_id<P::philox_unroll>(X.seed, X.id, X.n, k), 0u, 0};
       int k2 = 0;
       out.meta |= k << 24;
-      annihilate<P>(V, &k2, 1, out);
+      annihilate<P>(track_block<P::philox_unroll>(V.seed, V.id, V.n, 1u), V, &k2, 1, out);
     }
     return;
   }
@@ -444,7 +444,7 @@ AD_HD bool step_charged(Track<typename P::R>& t, int type, Creations<typename P:
   using F = Fmt<R>;
   using C = Consts<R>;
   const uint32_t n = t.ctr;
-  const U4 a = track_block<P::philox_unroll>(t.seed, t.id, n, 0u);  // block 1 is drawn only where it is used
+  const U4 a = track_block<P::philox_unroll>(t.seed, t.id, n, 0u);
   const Creator<P> X{t.seed, t.id, n, 0};
   int kidx = 0;
   const int v = t.vol, m = v & 1;
@@ -490,10 +490,14 @@ AD_HD bool step_charged(Track<typename P::R>& t, int type, Creations<typename P:
     if (type == POSITRON) dep.escaped += 2.0 * (double)C::me;
     return false;
   }
+  // Block 1 serves the interaction-length resample after a brem and the
+  // annihilation direction; one of the two occurs in nearly every wavefront, so
+  // it is drawn once here rather than on each path.
+  const U4 b = track_block<P::philox_unroll>(t.seed, t.id, n, 1u);
   if (E1 < C::cut_e) {
     dep.cut += (double)E1;
     t.vol = v1;
-    if (type == POSITRON) annihilate<P>(X, &kidx, 0, out);
+    if (type == POSITRON) annihilate<P>(b, X, &kidx, 0, out);
     return false;
   }
   const R th0 = (C::msc / E0) * F::sqrt_(sr_ / lam);
@@ -510,13 +514,12 @@ AD_HD bool step_charged(Track<typename P::R>& t, int type, Creations<typename P:
     const R E2 = E1 - k;
     k = E1 - E2;
     create<P>(X, &kidx, GAMMA, k, out, dep);
-    const U4 b = track_block<P::philox_unroll>(t.seed, t.id, n, 1u);
     nl = -plog<R>(P::uni(b.x));
     E = E2;
     if (E2 < C::cut_e) {
       dep.cut += (double)E2;
       t.vol = v1;
-      if (type == POSITRON) annihilate<P>(X, &kidx, 0, out);
+      if (type == POSITRON) annihilate<P>(b, X, &kidx, 0, out);
       return false;
     }
   }
@@ -538,9 +541,11 @@ AD_HD bool step_photon(Track<typename P::R>& t, Creations<typename P::R>& out, D
   const int v = t.vol, m = v & 1;
   const R E = t.E;
   R nl = t.nl;
-  // Random words are drawn only when used: a geometry-limited step of a photon
-  // whose interaction length is already sampled needs none.
-  if (nl < (R)0) nl = -plog<R>(P::uni(track_block<P::philox_unroll>(t.seed, t.id, n, 0u).x));
+  // Block 0 gives the initial interaction length and the interaction's split.
+  // Almost every wavefront holds a new photon and an interacting one, so the
+  // block is drawn once for all lanes instead of on each of the two paths.
+  const U4 a = track_block<P::philox_unroll>(t.seed, t.id, n, 0u);
+  if (nl < (R)0) nl = -plog<R>(P::uni(a.x));
   const bool pair = E > C::pairth;
   const R lam = pair ? C::lpair(m) : C::lcomp(m);
   const R s_phys = nl * lam;
@@ -558,7 +563,7 @@ AD_HD bool step_photon(Track<typename P::R>& t, Creations<typename P::R>& out, D
     return false;
   }
   t.vol = v1;
-  const uint32_t a3 = lim == LIM_PHYS ? track_block<P::philox_unroll>(t.seed, t.id, n, 0u).w : 0u;
+  const uint32_t a3 = a.w;
   if (lim == LIM_PHYS && pair) {
     R T, r;
     two_sum<R>(E, -C::pairth, &T, &r);
