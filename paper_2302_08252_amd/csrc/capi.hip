@@ -190,22 +190,18 @@ __global__ void k_group_energy(EventGroup* g, const adept_primary* p, unsigned l
   g[i].energy = e;
 }
 
-// Fold the per-block tally rows (single-event runs) into event 0's tallies, in
-// row order, and clear them.
+// Fold the per-block tally rows into the tallies, each entry summed over the
+// rows in row order, and clear the rows.
 __global__ void k_fold_rows(const KArgs a) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= kRowLen) return;
+  const unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.row_len) return;
   double s = 0.0;
-  for (unsigned r = 0; r < kMaxGrid; ++r) {
-    double* row = a.rows + (unsigned long long)r * kRowLen;
+  for (unsigned r = 0; r < a.n_rows; ++r) {
+    double* row = a.rows + (unsigned long long)r * a.row_len;
     s += row[i];
     row[i] = 0.0;
   }
-  if (s == 0.0) return;
-  if (i < kNumVol) a.cont[i] += s;
-  else if (i < 2 * kNumVol) a.cut[i - kNumVol] += s;
-  else if (i == 2 * kNumVol) a.esc[0] += s;
-  else a.rnd[0] += s;
+  if (s != 0.0) *tally_ptr(a, (uint32_t)i) += s;
 }
 
 __global__ void k_layer(const KArgs a, double* out) {
@@ -321,6 +317,7 @@ adept_status fail(adept_ctx* c, adept_status code, const std::string& msg) {
   } while (0)
 
 struct Plan {
+  size_t row_len, n_rows;
   size_t ctrl, buf[3][2], list[3][2], ring[3], desc[2], idesc[2], cont, cut, esc, rnd, ein, cells, rows, scratch, rw,
       heat[3][2], seeds, total;
   unsigned long long desc_words, idesc_words;
@@ -335,6 +332,18 @@ size_t bump(size_t& at, size_t bytes) {
 uint64_t buf_bytes_of(const adept_ctx* c) {
   return c->prec ? buffer_bytes<true>(c->layout.mapping, c->layout.aosoa_lanes, c->C)
                  : buffer_bytes<false>(c->layout.mapping, c->layout.aosoa_lanes, c->C);
+}
+
+// Tally rows: the flat tally index space of one block (202 per event, then the
+// cells).  A single event without cells keeps one row for every possible block;
+// otherwise kBatchRows rows cover the grid of 1024-lane blocks (2 per CU) and a
+// block beyond them adds to the tallies directly.
+constexpr size_t kBatchRows = 512;
+size_t row_len_of(const adept_ctx* c) {
+  return (size_t)kRowLen * c->seeds.size() + (size_t)kNumLayer * c->nx * c->ny;
+}
+size_t rows_of(const adept_ctx* c) {
+  return (c->seeds.size() == 1 && c->nx * c->ny == 0) ? (size_t)kMaxGrid : kBatchRows;
 }
 
 Plan plan(const adept_ctx* c) {
@@ -362,7 +371,9 @@ Plan plan(const adept_ctx* c) {
   P.ein = bump(at, E * 8);
   const size_t ncell = (size_t)kNumLayer * c->nx * c->ny;
   P.cells = ncell ? bump(at, ncell * 8) : 0;
-  P.rows = bump(at, (size_t)kMaxGrid * kRowLen * 8);
+  P.row_len = row_len_of(c);
+  P.n_rows = rows_of(c);
+  P.rows = bump(at, (size_t)P.n_rows * P.row_len * 8);
   P.scratch = bump(at, std::max<size_t>(E * kNumVol, ncell) * 8 + 8);
   P.rw = bump(at, 3 * 2 * 28 * 8);
   for (int t = 0; t < 3; ++t)
@@ -400,6 +411,8 @@ void fill_args(adept_ctx* c) {
   a.ein = (double*)(A + P.ein);
   a.cells = P.cells ? (double*)(A + P.cells) : nullptr;
   a.rows = (double*)(A + P.rows);
+  a.row_len = P.row_len;
+  a.n_rows = (unsigned)P.n_rows;
   a.nx = c->nx;
   a.ny = c->ny;
   a.pitch = c->pitch;
@@ -831,7 +844,7 @@ adept_status adept_tally(adept_ctx* c, adept_tally_kind kind, double* out, size_
   const KArgs& a = c->args;
   const double* src = nullptr;
   size_t want = 0;
-  hipLaunchKernelGGL(k_fold_rows, dim3(1), dim3(256), 0, c->stream, a);
+  hipLaunchKernelGGL(k_fold_rows, dim3((unsigned)((a.row_len + 255) / 256)), dim3(256), 0, c->stream, a);
   HIPCHK(hipStreamSynchronize(c->stream));
   switch (kind) {
     case ADEPT_T_DEP_CONT: src = a.cont; want = E * kNumVol; break;

@@ -101,7 +101,11 @@ struct KArgs {
   double* rnd;                 // [event]
   double* ein;                 // [event]
   double* cells;               // [50][nx][ny] or null
-  double* rows;                // single-event runs: one tally row per block index, kRowLen doubles
+  double* rows;                // one tally row per block index (row_len doubles, n_rows rows): partial sums
+                               // of the block's deposits, folded into the tallies when they are read
+  unsigned long long row_len;  // 202 * events + cells: the flat tally index space
+  unsigned n_rows;             // blocks at or beyond this index add to the tallies directly
+  unsigned pad_rows;
   uint32_t nx, ny;
   double pitch;
   double cell_hx, cell_hy;     // (0.5 * nx) * pitch, (0.5 * ny) * pitch
@@ -358,6 +362,17 @@ __device__ __forceinline__ double* tally_ptr(const KArgs& a, uint32_t key) {
   return a.cells + (key - 202u * E);
 }
 
+// Where a block's deposits go past its LDS cache: its own row while the launch
+// runs (only this block writes it, so the atomic need not leave the XCD), or
+// the tallies themselves for a block beyond the allocated rows.
+__device__ __forceinline__ void spill_add(const KArgs& a, uint32_t key, double v) {
+  if (blockIdx.x < a.n_rows)
+    __hip_atomic_fetch_add(a.rows + (unsigned long long)blockIdx.x * a.row_len + key, v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+  else
+    __hip_atomic_fetch_add(tally_ptr(a, key), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ void cache_add(const KArgs& a, TallyCache& tc, uint32_t key, double v) {
   const uint32_t h = (key * 2654435761u) >> (32 - kCacheBits);
   uint32_t cur = tc.key[h];
@@ -365,7 +380,7 @@ __device__ __forceinline__ void cache_add(const KArgs& a, TallyCache& tc, uint32
   if (cur == key) {
     __hip_atomic_fetch_add(&tc.val[h], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   } else {
-    __hip_atomic_fetch_add(tally_ptr(a, key), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    spill_add(a, key, v);
   }
 }
 
@@ -379,8 +394,7 @@ __device__ __forceinline__ void cache_init(TallyCache& tc) {
 __device__ __forceinline__ void cache_flush(const KArgs& a, TallyCache& tc) {
   __syncthreads();
   for (int i = threadIdx.x; i < kCacheSlots; i += blockDim.x)
-    if (tc.key[i] != kCacheEmpty && tc.val[i] != 0.0)
-      __hip_atomic_fetch_add(tally_ptr(a, tc.key[i]), tc.val[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tc.key[i] != kCacheEmpty && tc.val[i] != 0.0) spill_add(a, tc.key[i], tc.val[i]);
 }
 
 __device__ __forceinline__ void gadd(double* p, double v) {
@@ -437,7 +451,7 @@ __device__ __forceinline__ void book(const KArgs& a, TallyLDS* tl, TallyCache* t
 // tallies in a fixed order when the tallies are read.
 __device__ __forceinline__ void flush(const KArgs& a, TallyLDS& tl) {
   __syncthreads();
-  double* row = a.rows + (unsigned long long)blockIdx.x * kRowLen;
+  double* row = a.rows + (unsigned long long)blockIdx.x * a.row_len;
   for (int i = threadIdx.x; i < kRowLen; i += blockDim.x) {
     double v;
     if (i < kNumVol) v = tl.cont[i];
