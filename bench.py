@@ -197,17 +197,17 @@ def run_once(ad, torch, sim, prims=None, dev=None):
 
 def batched_section(ad, torch, np, workloads, args):
     """512 uneven events (cfg3): layout and launch picked by the autotuner on a
-    16-event sample, events admitted by the capacity rule, per-event tallies."""
+    64-event sample, events admitted by the capacity rule, per-event tallies."""
     wl = workloads.cfg3()
     kappa = kappa_cfg1()
     C = 1 << 24
     cands = [(1, 0, 1), (1, 1, 1), (1, 2, 16), (1, 2, 64), (1, 2, 256)]
-    sample = wl.primaries[wl.primaries["event"] < 16]  # ~16k primaries: peak ~5e6 photons < 2^23
-    layout, launch, _ = ad.adept_autotune_layout(ad.MIXED, 1 << 23, cands, wl.seeds[:16], sample)
+    sample = wl.primaries[wl.primaries["event"] < 64]  # ~64k primaries: peak below 1e7 photons < 2^24
+    layout, launch, _ = ad.adept_autotune_layout(ad.MIXED, 1 << 24, cands, wl.seeds[:64], sample)
     out = {"workload": wl.description, "capacity_per_type": C, "admission": {"alpha": 0.8, "kappa_per_GeV": kappa},
            "autotuned": {"layout": {"scheme": "dense" if layout[0] else "sparse",
                                     "mapping": ["AoS", "SoA", "AoSoA"][layout[1]], "lanes": layout[2]},
-                         "launch": launch, "tuning_sample": "events 0-15, capacity 2^23"}}
+                         "launch": launch, "tuning_sample": "events 0-63, capacity 2^24"}}
     sim = ad.Sim(layout[0], layout[1], ad.MIXED, C, layout[2], seeds=wl.seeds, admission=(0.8, kappa), launch=launch)
     dt, it, st = run_once(ad, torch, sim, wl.primaries)
     ts = sum(st["track_steps"])
@@ -245,7 +245,7 @@ def cfg4_section(ad, torch, np, workloads):
     C = 1 << 28
     kappa = kappa_cfg1()
     sim = ad.Sim(ad.DENSE_DOUBLE, ad.MAP_SOA, ad.MIXED, C, 64, seeds=wl.seeds, scoring=(100, 100, 4.0),
-                 admission=(0.8, kappa), launch={"block": 256, "graph_iters": 32})
+                 admission=(0.8, kappa), launch={"block": 1024, "graph_iters": 32})
     ad.adept_set_timing(sim.ctx, True)
     dt, it, st = run_once(ad, torch, sim, wl.primaries)
     cells = sim.tally(ad.T_CELLS)
@@ -272,7 +272,7 @@ def layout_study(ad, torch, np, workloads):
     res = {"workload": wl.description, "precision": "FP64", "timings": {}}
     for name, (s, m, n) in {"sparse AoS": (0, 0, 1), "dense AoS": (1, 0, 1), "dense SoA": (1, 1, 1),
                             "dense AoSoA-64": (1, 2, 64)}.items():
-        sim = ad.Sim(s, m, ad.FP64, C, n, seeds=wl.seeds, launch={"block": 256, "graph_iters": 32})
+        sim = ad.Sim(s, m, ad.FP64, C, n, seeds=wl.seeds, launch={"block": 1024, "graph_iters": 32})
         best = 1e9
         for r in range(3):
             dt, it, st = run_once(ad, torch, sim, wl.primaries, dev)
