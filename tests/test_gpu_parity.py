@@ -62,17 +62,21 @@ def compare_tallies(sim, o, oracle_mod, rtol=1e-12):
     assert np.all(np.abs(g - w) <= 1e-12 * o.tally(oracle_mod.T_EIN))
 
 
+@pytest.mark.parametrize("block", [64, 1024])
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("mapping,lanes", LAYOUTS)
 @pytest.mark.parametrize("scheme", SCHEMES)
-def test_iterations_bitwise(ad, oracle_mod, scheme, mapping, lanes, precision):
-    """12 primaries of 300 MeV (several tiles, ragged tails): state after every iteration."""
-    say(f"case iterations_bitwise scheme={scheme} mapping={mapping} lanes={lanes} precision={precision}")
-    C = 1 << 14
-    prims = np.concatenate([workloads.primaries(10, workloads.ELECTRON, 300.0),
-                            workloads.primaries(1, workloads.POSITRON, 40.0, first_id=10),
-                            workloads.primaries(1, workloads.GAMMA, 25.0, first_id=11)])
-    sim = ad.Sim(scheme, mapping, precision, C, lanes, seeds=[3], launch={"block": 64, "graph_iters": 8})
+def test_iterations_bitwise(ad, oracle_mod, scheme, mapping, lanes, precision, block):
+    """Primaries of 300 MeV to 3 GeV (several tiles, ragged tails): state after every
+    iteration.  Block 64 runs one track per lane; block 1024 runs two per lane under
+    the mixed policy, with a tile of 2048 tracks, so the larger workload there."""
+    say(f"case iterations_bitwise scheme={scheme} mapping={mapping} lanes={lanes} precision={precision} block={block}")
+    C = 1 << 16
+    n_e, e_e = (10, 300.0) if block == 64 else (40, 3000.0)
+    prims = np.concatenate([workloads.primaries(n_e, workloads.ELECTRON, e_e),
+                            workloads.primaries(1, workloads.POSITRON, 40.0, first_id=n_e),
+                            workloads.primaries(1, workloads.GAMMA, 25.0, first_id=n_e + 1)])
+    sim = ad.Sim(scheme, mapping, precision, C, lanes, seeds=[3], launch={"block": block, "graph_iters": 8})
     o = oracle_mod.Oracle(scheme, precision, C, [3])
     sim.inject(prims)
     assert o.inject(prims) == 0
@@ -97,7 +101,7 @@ def test_iterations_bitwise(ad, oracle_mod, scheme, mapping, lanes, precision):
     sim.close()
 
 
-@pytest.mark.parametrize("block", [64, 128, 256])
+@pytest.mark.parametrize("block", [64, 128, 256, 512, 1024])
 def test_cfg0_run_graph(ad, oracle_mod, block):
     """cfg0 as specified (sparse AoS FP64, 2^20 slots, 100 e- of 1 GeV, seed 1) through
     adept_run's graph replay: counts and stats exact, per-layer deposits 1e-12."""
@@ -203,17 +207,19 @@ def test_invalid_primaries_rejected(ad):
     sim.close()
 
 
-@pytest.mark.parametrize("precision,hold", [(0, 128), (1, 128), (1, 0), (0, 40)])
-def test_batched_admission_and_cells(ad, oracle_mod, precision, hold):
+@pytest.mark.parametrize("precision,hold,block", [(0, 128, 128), (1, 128, 1024), (1, 0, 128), (0, 40, 1024), (1, 40, 512)])
+def test_batched_admission_and_cells(ad, oracle_mod, precision, hold, block):
     """Uneven events of mixed particle types with per-event tallies, admission
     (with several reservation windows) and per-cell scoring, against the oracle
-    under the same admission rule."""
-    say(f"case batched precision={precision} hold={hold}")
+    under the same admission rule.  Block 128 runs more blocks than there are
+    tally rows (the rest add to the tallies directly); 512 and 1024 run tiles of
+    two tracks per lane under the mixed policy."""
+    say(f"case batched precision={precision} hold={hold} block={block}")
     wl = workloads.cfg3(n_events=24, max_per_event=6)
     kappa = [3.0, 2.0, 25.0]
     C = 1 << 14  # tight enough that admission staggers the events for hold > 0
     sim = ad.Sim(1, 1, precision, C, 1, seeds=wl.seeds, scoring=(100, 100, 4.0), admission=(0.8, kappa, hold),
-                 launch={"block": 128, "graph_iters": 16})
+                 launch={"block": block, "graph_iters": 16})
     o = oracle_mod.Oracle(oracle_mod.DENSE, precision, C, wl.seeds)
     o.set_scoring(100, 100, 4.0)
     o.set_admission(True, 0.8, kappa, hold)
