@@ -345,12 +345,12 @@ struct StatLDS {
 //   [201E, 202E) rounding, then the cells;
 // a lane whose slot holds another key adds to HBM directly; occupied slots are
 // added to HBM once per block at the end of the kernel.
-constexpr int kCacheBits = 11;
-constexpr int kCacheSlots = 1 << kCacheBits;
 constexpr uint32_t kCacheEmpty = 0xFFFFFFFFu;
+template <int BITS>
 struct TallyCache {
-  uint32_t key[kCacheSlots];
-  double val[kCacheSlots];
+  static constexpr int bits = BITS, slots = 1 << BITS;
+  uint32_t key[slots];
+  double val[slots];
 };
 
 __device__ __forceinline__ double* tally_ptr(const KArgs& a, uint32_t key) {
@@ -373,8 +373,9 @@ __device__ __forceinline__ void spill_add(const KArgs& a, uint32_t key, double v
     __hip_atomic_fetch_add(tally_ptr(a, key), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void cache_add(const KArgs& a, TallyCache& tc, uint32_t key, double v) {
-  const uint32_t h = (key * 2654435761u) >> (32 - kCacheBits);
+template <class TC>
+__device__ __forceinline__ void cache_add(const KArgs& a, TC& tc, uint32_t key, double v) {
+  const uint32_t h = (key * 2654435761u) >> (32 - TC::bits);
   uint32_t cur = tc.key[h];
   if (cur == kCacheEmpty) cur = atomicCAS(&tc.key[h], kCacheEmpty, key) == kCacheEmpty ? key : tc.key[h];
   if (cur == key) {
@@ -384,16 +385,18 @@ __device__ __forceinline__ void cache_add(const KArgs& a, TallyCache& tc, uint32
   }
 }
 
-__device__ __forceinline__ void cache_init(TallyCache& tc) {
-  for (int i = threadIdx.x; i < kCacheSlots; i += blockDim.x) {
+template <class TC>
+__device__ __forceinline__ void cache_init(TC& tc) {
+  for (int i = threadIdx.x; i < TC::slots; i += blockDim.x) {
     tc.key[i] = kCacheEmpty;
     tc.val[i] = 0.0;
   }
 }
 
-__device__ __forceinline__ void cache_flush(const KArgs& a, TallyCache& tc) {
+template <class TC>
+__device__ __forceinline__ void cache_flush(const KArgs& a, TC& tc) {
   __syncthreads();
-  for (int i = threadIdx.x; i < kCacheSlots; i += blockDim.x)
+  for (int i = threadIdx.x; i < TC::slots; i += blockDim.x)
     if (tc.key[i] != kCacheEmpty && tc.val[i] != 0.0) spill_add(a, tc.key[i], tc.val[i]);
 }
 
@@ -414,7 +417,8 @@ __device__ __forceinline__ uint32_t cell_index(const KArgs& a, int v, double x, 
 
 // Book one lane's deposits: pre-step volume v, event ev.  tl: single-event
 // LDS arrays; tc: LDS cache; neither: direct device atomics.
-__device__ __forceinline__ void book(const KArgs& a, TallyLDS* tl, TallyCache* tc, uint32_t ev, int v,
+template <class TC>
+__device__ __forceinline__ void book(const KArgs& a, TallyLDS* tl, TC* tc, uint32_t ev, int v,
                                      const Deposits& d, const double pos[3]) {
   if (tl) {
     if (d.cont != 0.0) ladd(&tl->cont[v], d.cont);
@@ -576,8 +580,8 @@ struct Park<R, true> {
   uint64_t id[kMaxBlock], aux[kMaxBlock];
   R dir[3][kMaxBlock], E[kMaxBlock], nl[kMaxBlock];
   R cE[3][kMaxBlock], cd[3][kMaxBlock];
-  uint32_t seed[kMaxBlock], ctr[kMaxBlock], vol[kMaxBlock], event[kMaxBlock], meta[kMaxBlock];
-  uint32_t flags[kMaxBlock];  // creations (2 bits), survived (bit 2), valid (bit 3)
+  uint32_t seed[kMaxBlock], ctr[kMaxBlock], vol[kMaxBlock], event[kMaxBlock];
+  uint32_t meta[kMaxBlock];  // creation metadata (bits 0-25), creations (26-27), survived (28), valid (29)
 };
 
 template <class R>
@@ -598,8 +602,7 @@ __device__ __forceinline__ void park(Park<R, true>& k, int i, const Track<R>& t,
   k.ctr[i] = t.ctr;
   k.vol[i] = (uint32_t)t.vol;
   k.event[i] = t.event;
-  k.meta[i] = cr.meta;
-  k.flags[i] = (uint32_t)cr.n | (surv ? 4u : 0u) | (valid ? 8u : 0u);
+  k.meta[i] = cr.meta | ((uint32_t)cr.n << 26) | (surv ? 1u << 28 : 0u) | (valid ? 1u << 29 : 0u);
 }
 
 template <class R>
@@ -620,11 +623,11 @@ __device__ __forceinline__ void unpark(const Park<R, true>& k, int i, Track<R>& 
   t.ctr = k.ctr[i];
   t.vol = (int32_t)k.vol[i];
   t.event = k.event[i];
-  cr.meta = k.meta[i];
-  const uint32_t f = k.flags[i];
-  cr.n = (int)(f & 3u);
-  surv = (f & 4u) != 0;
-  valid = (f & 8u) != 0;
+  const uint32_t m = k.meta[i];
+  cr.meta = m & ((1u << 26) - 1);
+  cr.n = (int)((m >> 26) & 3u);
+  surv = ((m >> 28) & 1u) != 0;
+  valid = ((m >> 29) & 1u) != 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -643,7 +646,7 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
   __shared__ Scan<NS, NV> sh;
   __shared__ Park<R, (TPT > 1)> pk;
   __shared__ TallyLDS tl;
-  __shared__ TallyCache tc;
+  __shared__ TallyCache<P::tally_cache_bits> tc;
   __shared__ StatLDS ss;
   Ctrl* c = a.ctrl;
   const uint32_t p = c->parity;
@@ -941,7 +944,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_inject(const KArgs a) {
           int kidx = 0;
           annihilate<P>(track_block<P::philox_unroll>(X.seed, X.id, X.n, 1u), X, &kidx, 0, cr);
         }
-        book(a, nullptr, nullptr, ev, t.vol, dep, t.pos);
+        book<TallyCache<P::tally_cache_bits>>(a, nullptr, nullptr, ev, t.vol, dep, t.pos);
       } else {
         keep = true;
       }

@@ -275,8 +275,9 @@ struct PolicyF64 {
   static constexpr bool mixed = false;
   static constexpr int philox_unroll = 5;  // measured fastest for this policy
   // tracks a lane of the step kernel holds per tile (the parked outputs of the
-  // earlier ones take LDS: the binary64 records do not fit twice)
-  AD_HD static constexpr int tracks_per_lane(int block) { return 1; }
+  // first take LDS: 148 B per lane here, so the batched tally cache is kept small)
+  AD_HD static constexpr int tracks_per_lane(int block) { return block >= 1024 ? 2 : 1; }
+  static constexpr int tally_cache_bits = 9;
   AD_HD static R uni(uint32_t r) { return u01(r); }
 };
 struct PolicyMixed {
@@ -284,6 +285,7 @@ struct PolicyMixed {
   static constexpr bool mixed = true;
   static constexpr int philox_unroll = 10;
   AD_HD static constexpr int tracks_per_lane(int block) { return block >= 1024 ? 2 : 1; }
+  static constexpr int tally_cache_bits = 11;
   AD_HD static R uni(uint32_t r) { return u01f(r); }
 };
 
