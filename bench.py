@@ -35,21 +35,32 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per step-kernel launch from the committed rocprofv3 --pmc summary
-    (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a plain copy of known
-    size), or None if the kernel sources changed since the counters were taken."""
+def profile_fields():
+    """The '- key: value' lines of the committed rocprofv3 --pmc summary of the
+    headline kernel, or {} if the kernel sources changed since it was taken."""
     try:
         text = open(TRAFFIC_SUMMARY).read()
     except OSError:
-        return None
+        return {}
     fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith("- ") and ":" in line)
     fields = {k[2:].strip(): v.strip() for k, v in fields.items()}
-    if fields.get("kernel source hash") != kernel_source_hash():
-        return None
+    return fields if fields.get("kernel source hash") == kernel_source_hash() else {}
+
+
+def measured_traffic():
+    """HBM bytes per step-kernel launch (FETCH_SIZE + WRITE_SIZE, scaled by the same
+    counters on a plain copy of known size), or None."""
     try:
-        return float(fields["scaled HBM bytes per launch"])
+        return float(profile_fields()["scaled HBM bytes per launch"])
     except (KeyError, ValueError):
+        return None
+
+
+def measured_lane_use():
+    """Active lanes per VALU instruction of the headline kernel (of 64), or None."""
+    try:
+        return float(profile_fields()["active lanes per VALU instruction"].split()[0])
+    except (KeyError, ValueError, IndexError):
         return None
 
 
@@ -104,6 +115,7 @@ def time_path(ad, torch, wl, dev_prims, scheme, mapping, precision, C, args, ste
         ad.adept_inject_device(sim.ctx, dev_prims.data_ptr(), n)
         sim.run()
     total = 0.0
+    runs = []
     per_run = None
     for k in range(steps):
         sim.reset()
@@ -113,7 +125,8 @@ def time_path(ad, torch, wl, dev_prims, scheme, mapping, precision, C, args, ste
         ad.adept_inject_device(sim.ctx, dev_prims.data_ptr(), n)
         iters = sim.run()
         torch.cuda.synchronize()
-        total += time.perf_counter() - t0
+        runs.append(time.perf_counter() - t0)
+        total += runs[-1]
         st = sim.stats()
         if per_run is None:
             per_run = dict(st, iterations=iters)
@@ -131,8 +144,10 @@ def time_path(ad, torch, wl, dev_prims, scheme, mapping, precision, C, args, ste
     closure_no_round = abs(ein.sum() - (tot - sim.tally(ad.T_ROUND).sum())) / ein.sum()
     sim.close()
     ts = sum(per_run["track_steps"])
+    mean = total / steps
+    cv = (sum((r - mean) ** 2 for r in runs) / steps) ** 0.5 / mean if steps > 1 else 0.0
     return {
-        "seconds": total, "ms_per_step": 1e3 * total / steps, "track_steps_per_run": ts,
+        "seconds": total, "ms_per_step": 1e3 * mean, "ms_min": 1e3 * min(runs), "cv": cv, "track_steps_per_run": ts,
         "track_steps_per_s": ts * steps / total, "primaries_per_s": n * steps / total,
         "iterations": per_run["iterations"], "stats": per_run, "layer": layer, "closure": closure,
         "closure_without_rounding_ledger": closure_no_round,
@@ -355,9 +370,11 @@ def main():
             "capacity_per_type": C, "block": args.block, "graph_iters": args.graph_iters,
         },
         "primaries_per_s": head["primaries_per_s"],
+        "timed_runs": {"ms_mean": head["ms_per_step"], "ms_min": head["ms_min"], "cv": head["cv"]},
         "track_steps_per_run": head["track_steps_per_run"],
         "iterations_per_run": head["iterations"],
         "divergent_wave_fraction": st["waves_divergent"] / max(st["waves"], 1),
+        "divergence_rate_rocprof": (1.0 - measured_lane_use() / 64.0) if measured_lane_use() else None,
         "closure_error": head["closure"],
         "roofline": {
             "bound": "hbm", "kernel": "k_step (fused transport step)",
