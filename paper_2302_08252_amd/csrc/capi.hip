@@ -190,17 +190,29 @@ __global__ void k_group_energy(EventGroup* g, const adept_primary* p, unsigned l
   g[i].energy = e;
 }
 
-// Fold the per-block tally rows into the tallies, each entry summed over the
-// rows in row order, and clear the rows.
-__global__ void k_fold_rows(const KArgs a) {
+// Fold the per-block tally rows into the tallies in two passes with a fixed
+// summation order: chunk c of the rows is summed per entry into part[c] (and the
+// rows are cleared), then the chunk sums are added in chunk order.
+__global__ void k_fold_part(const KArgs a, double* part, unsigned chunks) {
   const unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.row_len) return;
+  const unsigned c = blockIdx.y;
+  const unsigned r0 = (unsigned)((unsigned long long)a.n_rows * c / chunks);
+  const unsigned r1 = (unsigned)((unsigned long long)a.n_rows * (c + 1) / chunks);
   double s = 0.0;
-  for (unsigned r = 0; r < a.n_rows; ++r) {
+  for (unsigned r = r0; r < r1; ++r) {
     double* row = a.rows + (unsigned long long)r * a.row_len;
     s += row[i];
     row[i] = 0.0;
   }
+  part[(unsigned long long)c * a.row_len + i] = s;
+}
+
+__global__ void k_fold_rows(const KArgs a, const double* part, unsigned chunks) {
+  const unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.row_len) return;
+  double s = 0.0;
+  for (unsigned c = 0; c < chunks; ++c) s += part[(unsigned long long)c * a.row_len + i];
   if (s != 0.0) *tally_ptr(a, (uint32_t)i) += s;
 }
 
@@ -291,6 +303,8 @@ struct adept_ctx {
   bool admission_started = false;
   unsigned long long* dev_bad = nullptr;
   double* scratch = nullptr;  // readback scratch (n_events * 100 or cells)
+  double* fold = nullptr;     // chunk sums of the tally rows
+  unsigned fold_chunks = 1;
   // per-launch timing of the step kernel (adept_set_timing)
   int timing = 0;
   std::vector<hipEvent_t> ev;
@@ -317,7 +331,7 @@ adept_status fail(adept_ctx* c, adept_status code, const std::string& msg) {
   } while (0)
 
 struct Plan {
-  size_t row_len, n_rows;
+  size_t row_len, n_rows, fold_chunks, fold;
   size_t ctrl, buf[3][2], list[3][2], ring[3], desc[2], idesc[2], cont, cut, esc, rnd, ein, cells, rows, scratch, rw,
       heat[3][2], seeds, total;
   unsigned long long desc_words, idesc_words;
@@ -378,6 +392,8 @@ Plan plan(const adept_ctx* c) {
   P.n_rows = rows_of(c);
   P.rows = bump(at, (size_t)P.n_rows * P.row_len * 8);
   P.scratch = bump(at, std::max<size_t>(E * kNumVol, ncell) * 8 + 8);
+  P.fold_chunks = std::min<size_t>(64, std::max<size_t>(1, P.n_rows / 64));
+  P.fold = bump(at, P.fold_chunks * P.row_len * 8);
   P.rw = bump(at, 3 * 2 * 28 * 8);
   for (int t = 0; t < 3; ++t)
     for (int b = 0; b < 2; ++b) P.heat[t][b] = (c->instr_on && (b == 0 || dense)) ? bump(at, bb) : 0;
@@ -439,6 +455,8 @@ void fill_args(adept_ctx* c) {
   a.hold = c->hold;
   a.count_empty = 1;
   c->scratch = (double*)(A + P.scratch);
+  c->fold = (double*)(A + P.fold);
+  c->fold_chunks = (unsigned)P.fold_chunks;
   c->buf_bytes = buf_bytes_of(c);
 }
 
@@ -847,7 +865,11 @@ adept_status adept_tally(adept_ctx* c, adept_tally_kind kind, double* out, size_
   const KArgs& a = c->args;
   const double* src = nullptr;
   size_t want = 0;
-  hipLaunchKernelGGL(k_fold_rows, dim3((unsigned)((a.row_len + 255) / 256)), dim3(256), 0, c->stream, a);
+  const unsigned fold_blocks = (unsigned)((a.row_len + 255) / 256);
+  hipLaunchKernelGGL(k_fold_part, dim3(fold_blocks, c->fold_chunks), dim3(256), 0, c->stream, a, c->fold,
+                     c->fold_chunks);
+  hipLaunchKernelGGL(k_fold_rows, dim3(fold_blocks), dim3(256), 0, c->stream, a, (const double*)c->fold,
+                     c->fold_chunks);
   HIPCHK(hipStreamSynchronize(c->stream));
   switch (kind) {
     case ADEPT_T_DEP_CONT: src = a.cont; want = E * kNumVol; break;
