@@ -159,10 +159,36 @@ __device__ __forceinline__ T row_scan(T x) {  // inclusive, within each row of 1
   return x;
 }
 __device__ __forceinline__ uint32_t lane_value(uint32_t x, int l) { return __builtin_amdgcn_readlane(x, l); }
+// (readlane yields a signed int: both halves are zero-extended before they are joined)
 __device__ __forceinline__ unsigned long long lane_value(unsigned long long x, int l) {
-  return ((unsigned long long)__builtin_amdgcn_readlane((uint32_t)(x >> 32), l) << 32) |
-         __builtin_amdgcn_readlane((uint32_t)x, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+  return ((unsigned long long)hi << 32) | lo;
 }
+__device__ __forceinline__ double row_shr_f64(double x, int k) {
+  const unsigned long long u = __double_as_longlong(x);
+  unsigned long long r = 0;
+  switch (k) {
+    case 1: r = row_shr<1>(u); break;
+    case 2: r = row_shr<2>(u); break;
+    case 4: r = row_shr<4>(u); break;
+    default: r = row_shr<8>(u); break;
+  }
+  return __longlong_as_double((long long)r);
+}
+// Sum of a double over the 64 lanes of a wavefront (every lane active; fixed
+// order); uniform result.
+__device__ __forceinline__ double wave_sum_f64(double v) {
+  v += row_shr_f64(v, 1);
+  v += row_shr_f64(v, 2);
+  v += row_shr_f64(v, 4);
+  v += row_shr_f64(v, 8);
+  const unsigned long long u = __double_as_longlong(v);
+  return ((__longlong_as_double((long long)lane_value(u, 15)) + __longlong_as_double((long long)lane_value(u, 31))) +
+          __longlong_as_double((long long)lane_value(u, 47))) +
+         __longlong_as_double((long long)lane_value(u, 63));
+}
+
 // Inclusive scan over the 64 lanes of a wavefront (every lane active).
 __device__ __forceinline__ uint32_t wave_scan(uint32_t x) {
   x = row_scan(x);
@@ -402,6 +428,22 @@ __device__ __forceinline__ void cache_flush(const KArgs& a, TC& tc) {
 
 __device__ __forceinline__ void gadd(double* p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// base[key] += v over the lanes of a wavefront (every lane calls it, inactive
+// ones with v = 0): one device atomic per distinct key per wavefront instead of
+// one per lane on the same address.
+__device__ __forceinline__ void wave_gadd_keyed(double* base, uint32_t key, double v) {
+  const int lane = __lane_id();
+  unsigned long long pending = __ballot(v != 0.0);
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const uint32_t k = __builtin_amdgcn_readlane(key, leader);
+    const unsigned long long m = __ballot(((pending >> lane) & 1ull) && key == k);
+    const double s = wave_sum_f64(((m >> lane) & 1ull) ? v : 0.0);
+    if (lane == leader) gadd(base + k, s);
+    pending &= ~m;
+  }
 }
 __device__ __forceinline__ void ladd(double* p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -913,10 +955,13 @@ __global__ void __launch_bounds__(kMaxBlock) k_inject(const KArgs a) {
     Deposits dep{0.0, 0.0, 0.0, 0.0, {0.0, 0.0}};
     int type = 0;
     bool keep = false;
+    double ein = 0.0, ein2 = 0.0, rnd = 0.0;  // input energy, positron rest mass, rounding residual
+    uint32_t evk = 0;
     if (valid) {
       const adept_primary q0 = a.staged[idx];
       type = q0.type;
       const uint32_t ev = q0.event;
+      evk = ev;
       t.pos[0] = q0.pos[0];
       t.pos[1] = q0.pos[1];
       t.pos[2] = q0.pos[2];
@@ -930,12 +975,9 @@ __global__ void __launch_bounds__(kMaxBlock) k_inject(const KArgs a) {
       t.ctr = 0;
       t.vol = locate(q0.pos[2]);
       t.event = ev;
-      gadd(&a.ein[ev], q0.E);
-      if (type == POSITRON) gadd(&a.ein[ev], 2.0 * (double)Consts<R>::me);
-      if (P::mixed) {
-        const double r = q0.E - (double)t.E;
-        if (r != 0.0) gadd(&a.rnd[ev], r);
-      }
+      ein = q0.E;
+      if (type == POSITRON) ein2 = 2.0 * (double)Consts<R>::me;
+      if (P::mixed) rnd = q0.E - (double)t.E;
       const bool subcut = type == GAMMA ? (t.E < Consts<R>::cut_g) : (t.E < Consts<R>::cut_e);
       if (subcut) {
         dep.cut = (double)t.E;
@@ -949,6 +991,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_inject(const KArgs a) {
         keep = true;
       }
     }
+    // energy ledger of the event, reduced per wavefront (every lane is active here)
+    wave_gadd_keyed(a.ein, evk, ein);
+    wave_gadd_keyed(a.ein, evk, ein2);
+    if (P::mixed) wave_gadd_keyed(a.rnd, evk, rnd);
     uint32_t cnt[NV] = {0, 0, 0};
     if (valid) {
 #pragma unroll
