@@ -209,6 +209,26 @@ adept_status adept_tally(adept_ctx* ctx, adept_tally_kind kind, double* out, siz
 adept_status adept_access_counts(adept_ctx* ctx, adept_particle t, uint32_t buffer, uint64_t reads[14],
                                  uint64_t writes[14], uint32_t* heat_words, size_t n_words);
 
+/* Access counts of one physical buffer at the granularity the memory system
+ * moves (the heatmaps of Sec. 5, per cache line): out[i] is the sum of the
+ * per-4-byte-word counters of bytes [i * line_bytes, (i + 1) * line_bytes).
+ * line_bytes is 64 or 128; n_lines must equal ceil(buffer bytes / line_bytes).
+ * Needs an instrumented context (ADEPT_E_STATE otherwise).  Synchronous;
+ * allocates device memory for the reduction. */
+adept_status adept_line_heat(adept_ctx* ctx, adept_particle t, uint32_t buffer, uint32_t line_bytes, uint64_t* out,
+                             size_t n_lines);
+
+/* The record layouts of Sec. 3 as a byte picture: for bytes [first_byte,
+ * first_byte + n) of one track buffer of the given layout, precision and
+ * capacity (validated as by adept_create), the field stored there (0-13, in
+ * the order of adept_track_host: pos x y z, dir x y z, E, numIALeft, trackId,
+ * parentId, rngSeed, rngCtr, volume, event) or -1 for padding or bytes past
+ * the buffer's end.  If total_bytes is not NULL it receives the buffer's byte
+ * size (what adept_buffer_bytes reports for such a context).  leaf_out may be
+ * NULL when n is 0.  Host-only; no context, no device, nothing allocated. */
+adept_status adept_layout_map(adept_layout layout, adept_precision precision, uint64_t capacity, uint64_t first_byte,
+                              uint64_t n, int8_t* leaf_out, uint64_t* total_bytes);
+
 /* Byte size of one physical track buffer of this context. */
 adept_status adept_buffer_bytes(const adept_ctx* ctx, size_t* bytes);
 

@@ -51,6 +51,7 @@ EXPORTS = [
     "adept_create", "adept_arena_bytes", "adept_bind", "adept_set_events", "adept_set_scoring",
     "adept_set_admission", "adept_set_instrumented", "adept_set_launch", "adept_get_launch", "adept_inject",
     "adept_inject_device", "adept_step", "adept_run", "adept_tally", "adept_access_counts", "adept_buffer_bytes",
+    "adept_line_heat", "adept_layout_map",
     "adept_stats_get", "adept_dump_tracks", "adept_dump_ring", "adept_reset", "adept_autotune",
     "adept_set_timing", "adept_autotune_layout", "adept_last_error", "adept_destroy",
 ]
@@ -84,6 +85,8 @@ def lib():
         "adept_tally": (i32, [P, i32, P, sz]),
         "adept_access_counts": (i32, [P, i32, u32, P, P, P, sz]),
         "adept_buffer_bytes": (i32, [P, P]),
+        "adept_line_heat": (i32, [P, i32, u32, u32, P, sz]),
+        "adept_layout_map": (i32, [Layout, i32, u64, u64, u64, P, P]),
         "adept_stats_get": (i32, [P, P]),
         "adept_dump_tracks": (i32, [P, i32, P, P, u64, P]),
         "adept_dump_ring": (i32, [P, i32, P, u64, P, P]),
@@ -205,6 +208,36 @@ def adept_access_counts(ctx, ptype, buffer=0, heat=False):
     rc = lib().adept_access_counts(ctx, ptype, buffer, _ptr(r), _ptr(w), _ptr(hw) if heat else None, len(hw))
     _check(ctx, rc, "adept_access_counts")
     return (r, w, hw) if heat else (r, w)
+
+
+def adept_line_heat(ctx, ptype, buffer=0, line_bytes=128):
+    out = np.zeros(-(-adept_buffer_bytes(ctx) // line_bytes), dtype=np.uint64)
+    _check(ctx, lib().adept_line_heat(ctx, ptype, buffer, line_bytes, _ptr(out), len(out)), "adept_line_heat")
+    return out
+
+
+def adept_layout_map(mapping, precision, capacity, first_byte=0, n=None, aosoa_lanes=64):
+    """Field id (0-13, -1 padding) of each byte of a track buffer; n defaults to the rest of the buffer."""
+    lay = Layout(0, mapping, aosoa_lanes if mapping == MAP_AOSOA else 1)
+    total = ctypes.c_uint64()
+    _check(None, lib().adept_layout_map(lay, precision, capacity, 0, 0, None, ctypes.byref(total)), "adept_layout_map")
+    if n is None:
+        n = max(total.value - first_byte, 0)
+    out = np.zeros(n, dtype=np.int8)
+    _check(None, lib().adept_layout_map(lay, precision, capacity, first_byte, n, _ptr(out), None), "adept_layout_map")
+    return out
+
+
+def layout_picture(leaf_map, bytes_per_row=128, rows=8):
+    """Text picture of a byte map: one character per 4-byte word (field id in base 36, '.' padding)."""
+    glyph = "0123456789abcd"
+    words = leaf_map[: len(leaf_map) // 4 * 4].reshape(-1, 4)[:, 0]
+    per_row = bytes_per_row // 4
+    lines = []
+    for r in range(min(rows, -(-len(words) // per_row))):
+        w = words[r * per_row:(r + 1) * per_row]
+        lines.append("".join("." if x < 0 else glyph[x] for x in w))
+    return "\n".join(lines)
 
 
 def adept_stats_get(ctx):
@@ -343,6 +376,9 @@ class Sim:
 
     def access_counts(self, ptype, buffer=0, heat=False):
         return adept_access_counts(self.ctx, ptype, buffer, heat)
+
+    def line_heat(self, ptype, buffer=0, line_bytes=128):
+        return adept_line_heat(self.ctx, ptype, buffer, line_bytes)
 
     def reset(self):
         adept_reset(self.ctx)

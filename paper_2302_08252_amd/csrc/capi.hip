@@ -641,6 +641,45 @@ adept_status inject_staged(adept_ctx* c, unsigned long long n) {
 
 }  // namespace
 
+// Sum of the per-word access counters over each line of words_per_line words.
+__global__ void k_line_heat(const uint32_t* heat, unsigned long long n_words, uint32_t words_per_line,
+                            unsigned long long* out, unsigned long long n_lines) {
+  const unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_lines) return;
+  const unsigned long long w0 = i * words_per_line;
+  const unsigned long long w1 = std::min<unsigned long long>(w0 + words_per_line, n_words);
+  unsigned long long s = 0;
+  for (unsigned long long w = w0; w < w1; ++w) s += heat[w];
+  out[i] = s;
+}
+
+namespace {
+// The field stored at byte b of a track buffer (-1: padding or beyond the
+// capacity): the inverse of leaf_addr, byte by byte.
+template <bool MIXED>
+int leaf_at(int map, const MapArgs& m, uint64_t lanes, uint64_t C, uint64_t b) {
+  using RC = Rec<MIXED>;
+  if (map == MAP_AOS) {
+    const uint64_t s = b / RC::stride, o = b % RC::stride;
+    if (s >= C) return -1;
+    for (int l = 0; l < 14; ++l)
+      if (o >= RC::off(l) && o < RC::off(l) + RC::size(l)) return l;
+    return -1;
+  }
+  if (map == MAP_SOA) {
+    for (int l = 0; l < 14; ++l)
+      if (b >= m.soa_start[l] && b < m.soa_start[l] + C * RC::size(l)) return l;
+    return -1;
+  }
+  const uint64_t blk = (uint64_t)RC::bytes * lanes, k = b / blk, o = b % blk;
+  for (int l = 0; l < 14; ++l) {
+    const uint64_t lo = (uint64_t)RC::prefix(l) * lanes, hi = lo + (uint64_t)RC::size(l) * lanes;
+    if (o >= lo && o < hi) return k * lanes + (o - lo) / RC::size(l) < C ? l : -1;
+  }
+  return -1;
+}
+}  // namespace
+
 // ---------------------------------------------------------------------------
 // ABI
 // ---------------------------------------------------------------------------
@@ -929,6 +968,49 @@ adept_status adept_access_counts(adept_ctx* c, adept_particle t, uint32_t buffer
       HIPCHK(hipMemcpy(heat_words, a.heat[t][buffer], n_words * 4, hipMemcpyDeviceToHost));
     }
   }
+  return ADEPT_OK;
+}
+
+adept_status adept_line_heat(adept_ctx* c, adept_particle t, uint32_t buffer, uint32_t line_bytes, uint64_t* out,
+                             size_t n_lines) {
+  if (!c || !out || t < 0 || t > 2 || buffer > 1 || (line_bytes != 64 && line_bytes != 128)) return ADEPT_E_INVALID;
+  if (buffer == 1 && c->layout.scheme != ADEPT_DENSE_DOUBLE) return fail(c, ADEPT_E_INVALID, "sparse has one buffer");
+  if (c->state == CREATED) return fail(c, ADEPT_E_STATE, "no state yet");
+  const KArgs& a = c->args;
+  if (!a.heat[t][buffer]) return fail(c, ADEPT_E_STATE, "not instrumented");
+  const unsigned long long lines = (c->buf_bytes + line_bytes - 1) / line_bytes;
+  if (n_lines != lines) return fail(c, ADEPT_E_INVALID, "n_lines must be ceil(buffer bytes / line_bytes)");
+  unsigned long long* d = nullptr;
+  HIPCHK(hipMalloc(&d, lines * 8));
+  hipLaunchKernelGGL(k_line_heat, dim3((unsigned)((lines + 255) / 256)), dim3(256), 0, c->stream, a.heat[t][buffer],
+                     (unsigned long long)(c->buf_bytes / 4), line_bytes / 4, d, lines);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(out, d, lines * 8, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(d);
+  if (e != hipSuccess) return fail(c, ADEPT_E_DEVICE, hipGetErrorString(e));
+  return ADEPT_OK;
+}
+
+adept_status adept_layout_map(adept_layout layout, adept_precision precision, uint64_t capacity, uint64_t first_byte,
+                              uint64_t n, int8_t* leaf_out, uint64_t* total_bytes) {
+  if ((n && !leaf_out) || layout.mapping < 0 || layout.mapping > 2) return ADEPT_E_INVALID;
+  if (precision != ADEPT_FP64 && precision != ADEPT_MIXED) return ADEPT_E_INVALID;
+  if (capacity == 0 || capacity > (1ull << 30)) return ADEPT_E_INVALID;
+  uint32_t lanes = 1;
+  if (layout.mapping == ADEPT_MAP_AOSOA) {
+    lanes = layout.aosoa_lanes;
+    if (lanes < 2 || lanes > 256 || (lanes & (lanes - 1)) || capacity % lanes) return ADEPT_E_INVALID;
+  }
+  const bool mixed = precision == ADEPT_MIXED;
+  if (total_bytes)
+    *total_bytes = mixed ? buffer_bytes<true>(layout.mapping, lanes, capacity)
+                         : buffer_bytes<false>(layout.mapping, lanes, capacity);
+  const MapArgs m = mixed ? make_map_args<true>(layout.mapping, lanes, capacity)
+                          : make_map_args<false>(layout.mapping, lanes, capacity);
+  for (uint64_t i = 0; i < n; ++i)
+    leaf_out[i] = (int8_t)(mixed ? leaf_at<true>(layout.mapping, m, lanes, capacity, first_byte + i)
+                                 : leaf_at<false>(layout.mapping, m, lanes, capacity, first_byte + i));
   return ADEPT_OK;
 }
 

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -57,3 +58,52 @@ def test_create_rejects_bad_arguments():
     assert L.adept_create(ad.Layout(0, 0, 1), 0, 0, ctypes.byref(h)) == ad.E_INVALID
     assert L.adept_create(ad.Layout(0, 0, 1), 0, (1 << 30) + 1, ctypes.byref(h)) == ad.E_INVALID
     L.adept_destroy(None)
+
+
+def _oracle_byte_map(oracle_mod, mapping, lanes, precision, capacity):
+    """The oracle's byte map of a layout: every (slot, field) placed at its address."""
+    total = oracle_mod.buffer_bytes(mapping, lanes, precision, capacity)
+    m = np.full(total, -1, dtype=np.int8)
+    for slot in range(capacity):
+        for leaf in range(14):
+            a = oracle_mod.leaf_addr(mapping, lanes, precision, capacity, slot, leaf)
+            n = oracle_mod.leaf_size(precision, leaf)
+            assert (m[a:a + n] == -1).all()  # no two fields share a byte
+            m[a:a + n] = leaf
+    return m
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("mapping,lanes,capacity", [(0, 1, 96), (1, 1, 96), (1, 1, 77), (2, 8, 96), (2, 64, 128),
+                                                    (2, 2, 6)])
+def test_layout_map_matches_oracle_byte_map(oracle_mod, mapping, lanes, capacity, precision):
+    """The library's byte picture of a layout (inverse address arithmetic) equals the
+    oracle's forward map, padding included, also through a window and past the end."""
+    import paper_2302_08252_amd as ad
+
+    if not os.path.exists(ad.LIB_PATH):
+        pytest.skip("libadept.so not built")
+    want = _oracle_byte_map(oracle_mod, mapping, lanes, precision, capacity)
+    got = ad.adept_layout_map(mapping, precision, capacity, aosoa_lanes=lanes)
+    assert np.array_equal(got, want)
+    win = ad.adept_layout_map(mapping, precision, capacity, first_byte=37, n=len(want), aosoa_lanes=lanes)
+    assert np.array_equal(win[:len(want) - 37], want[37:]) and (win[len(want) - 37:] == -1).all()
+    pic = ad.layout_picture(got, 64, 4).split("\n")
+    assert len(pic) == min(4, -(-len(want) // 64)) and all(len(r) <= 16 for r in pic)
+
+
+def test_layout_map_rejects_bad_arguments():
+    import paper_2302_08252_amd as ad
+
+    if not os.path.exists(ad.LIB_PATH):
+        pytest.skip("libadept.so not built")
+    L = ad.lib()
+    buf = np.zeros(8, dtype=np.int8)
+    p = buf.ctypes.data_as(ctypes.c_void_p)
+    assert L.adept_layout_map(ad.Layout(0, 2, 3), 0, 96, 0, 8, p, None) == ad.E_INVALID
+    assert L.adept_layout_map(ad.Layout(0, 2, 64), 0, 100, 0, 8, p, None) == ad.E_INVALID
+    assert L.adept_layout_map(ad.Layout(0, 3, 1), 0, 96, 0, 8, p, None) == ad.E_INVALID
+    assert L.adept_layout_map(ad.Layout(0, 0, 1), 2, 96, 0, 8, p, None) == ad.E_INVALID
+    assert L.adept_layout_map(ad.Layout(0, 0, 1), 0, 0, 0, 8, p, None) == ad.E_INVALID
+    assert L.adept_layout_map(ad.Layout(0, 0, 1), 0, 96, 0, 8, None, None) == ad.E_INVALID
+    assert L.adept_layout_map(ad.Layout(0, 0, 1), 0, 96, 0, 0, None, None) == ad.OK

@@ -165,7 +165,12 @@ def test_instrumented_counts_and_heatmaps(ad, oracle_mod, scheme, mapping, lanes
             r, w, h = sim.access_counts(t, b, heat=True)
             rr, ww = o.access_totals(t, b)
             assert np.array_equal(r, rr) and np.array_equal(w, ww), (t, b, r, rr, w, ww)
-            assert np.array_equal(h, o.heat_words(t, b, mapping, lanes)), (t, b)
+            want = o.heat_words(t, b, mapping, lanes)
+            assert np.array_equal(h, want), (t, b)
+            for lb in (64, 128):  # per-cache-line heat, ragged last line included
+                pad = np.zeros(-len(want) % (lb // 4), dtype=np.uint64)
+                lines = np.concatenate([want.astype(np.uint64), pad]).reshape(-1, lb // 4).sum(axis=1)
+                assert np.array_equal(sim.line_heat(t, b, lb), lines), (t, b, lb)
     sim.close()
 
 
