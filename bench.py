@@ -311,6 +311,29 @@ def layout_study(ad, torch, np, workloads):
         sim.close()
         counts[name] = rec
     res["instrumented_first_20_iterations"] = counts
+    # Cache-line view (Sec. 5 heatmaps at the granularity HBM moves): each 128-byte
+    # line is taken to move once per access of its most accessed word, so the bytes
+    # moved are 128 x the per-line maxima and the bytes used are 4 x the word counts.
+    lines = {}
+    for name, (s, m, n) in {"sparse AoS": (0, 0, 1), "sparse SoA": (0, 1, 1), "dense AoS": (1, 0, 1),
+                            "dense SoA": (1, 1, 1), "dense AoSoA-64": (1, 2, 64)}.items():
+        sim = ad.Sim(s, m, ad.FP64, C, n, seeds=wl.seeds, instrumented=20)
+        sim.inject(wl.primaries)
+        sim.run(20)
+        used = moved = touched = 0
+        for t in range(3):
+            for b in range(2 if s else 1):
+                words = sim.access_counts(t, b, heat=True)[2].astype(np.uint64)
+                lh = sim.line_heat(t, b, 128)
+                words = np.concatenate([words, np.zeros(-len(words) % 32, dtype=np.uint64)]).reshape(-1, 32)
+                assert np.array_equal(words.sum(axis=1), lh)
+                used += 4 * int(words.sum())
+                moved += 128 * int(words.max(axis=1).sum())
+                touched += int(np.count_nonzero(lh))
+        sim.close()
+        lines[name] = {"bytes_used": used, "bytes_moved_line_model": moved, "useful_fraction": used / max(moved, 1),
+                       "lines_touched": touched}
+    res["cache_lines_first_20_iterations"] = lines
     sp, dn = counts["sparse AoS"], counts["dense AoS"]
     res["paper_claims"] = {
         "slots_touched_sparse_vs_dense_electrons": [sp["electrons"]["slots_touched"], dn["electrons"]["slots_touched"]],
