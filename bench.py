@@ -334,6 +334,16 @@ def layout_study(ad, torch, np, workloads):
         lines[name] = {"bytes_used": used, "bytes_moved_line_model": moved, "useful_fraction": used / max(moved, 1),
                        "lines_touched": touched}
     res["cache_lines_first_20_iterations"] = lines
+    # Per-particle-type layouts (Sec. 6 future work): the per-type autotuner over
+    # the sparse single buffer's AoS / SoA / AoSoA-64, on the whole workload.
+    steps = sum(st["track_steps"])
+    cands = [(0, 0, 1), (0, 1, 1), (0, 2, 64)]
+    lay, launch, ms = ad.adept_autotune_type_layouts(ad.FP64, C, cands, wl.seeds, wl.primaries)
+    names = {(0, 1): "AoS", (1, 1): "SoA", (2, 64): "AoSoA-64"}
+    res["per_type_layouts_sparse"] = {
+        "autotuned": {t: names.get(tuple(l), str(l)) for t, l in zip(("electrons", "positrons", "photons"), lay)},
+        "launch": launch, "ms": ms, "track_steps_per_s": steps / (ms * 1e-3),
+        "note": "per-type contexts address every field through one general mapping form"}
     sp, dn = counts["sparse AoS"], counts["dense AoS"]
     res["paper_claims"] = {
         "slots_touched_sparse_vs_dense_electrons": [sp["electrons"]["slots_touched"], dn["electrons"]["slots_touched"]],

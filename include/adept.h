@@ -136,6 +136,15 @@ typedef struct {
  * capacity are fixed for the context's lifetime.  Errors: ADEPT_E_INVALID. */
 adept_status adept_create(adept_layout layout, adept_precision precision, uint64_t capacity, adept_ctx** out);
 
+/* Create a context whose particle types keep their tracks in different record
+ * layouts (the per-particle-type layouts proposed in Sec. 6): layouts[t] is the
+ * mapping of type t's buffers (electron, positron, photon), each validated as
+ * by adept_create; the three must name the same scheme.  Every access goes
+ * through one general form of the three mappings, so results equal those of
+ * adept_create for any choice.  Errors: ADEPT_E_INVALID. */
+adept_status adept_create_typed(const adept_layout layouts[3], adept_precision precision, uint64_t capacity,
+                                adept_ctx** out);
+
 /* Device bytes the context needs with its current settings (events, scoring,
  * instrumentation).  Valid before adept_bind. */
 adept_status adept_arena_bytes(const adept_ctx* ctx, size_t* bytes);
@@ -229,8 +238,12 @@ adept_status adept_line_heat(adept_ctx* ctx, adept_particle t, uint32_t buffer, 
 adept_status adept_layout_map(adept_layout layout, adept_precision precision, uint64_t capacity, uint64_t first_byte,
                               uint64_t n, int8_t* leaf_out, uint64_t* total_bytes);
 
-/* Byte size of one physical track buffer of this context. */
+/* Byte size of one physical track buffer of this context (ADEPT_E_INVALID for
+ * a context made by adept_create_typed: use adept_type_buffer_bytes). */
 adept_status adept_buffer_bytes(const adept_ctx* ctx, size_t* bytes);
+
+/* Byte size of one physical track buffer of particle type t. */
+adept_status adept_type_buffer_bytes(const adept_ctx* ctx, adept_particle t, size_t* bytes);
 
 adept_status adept_stats_get(adept_ctx* ctx, adept_stats* out);
 
@@ -267,6 +280,18 @@ adept_status adept_autotune_layout(adept_precision precision, uint64_t capacity,
                                    uint32_t n_candidates, uint32_t n_events, const uint32_t* seeds,
                                    const adept_primary* p, uint64_t n, adept_layout* best_layout,
                                    adept_launch* best_launch, double* best_ms);
+
+/* Per-type layout autotuner (Sec. 6): the candidates (one scheme) are first
+ * timed as a layout shared by all types, each with its tuned launch, as in
+ * adept_autotune_layout; then, in the order electron, positron, photon, each
+ * type moves to another candidate when that makes the whole run more than 2%
+ * faster (with the launch of the best shared layout).  Contexts made with
+ * adept_create_typed; best[t] receives the layout of type t.  Results never
+ * depend on the choice. */
+adept_status adept_autotune_type_layouts(adept_precision precision, uint64_t capacity, const adept_layout* candidates,
+                                         uint32_t n_candidates, uint32_t n_events, const uint32_t* seeds,
+                                         const adept_primary* p, uint64_t n, adept_layout best[3],
+                                         adept_launch* best_launch, double* best_ms);
 
 /* Last error message of this context (valid until the next call on it). */
 const char* adept_last_error(const adept_ctx* ctx);

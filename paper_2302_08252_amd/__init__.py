@@ -51,7 +51,8 @@ EXPORTS = [
     "adept_create", "adept_arena_bytes", "adept_bind", "adept_set_events", "adept_set_scoring",
     "adept_set_admission", "adept_set_instrumented", "adept_set_launch", "adept_get_launch", "adept_inject",
     "adept_inject_device", "adept_step", "adept_run", "adept_tally", "adept_access_counts", "adept_buffer_bytes",
-    "adept_line_heat", "adept_layout_map",
+    "adept_line_heat", "adept_layout_map", "adept_create_typed", "adept_type_buffer_bytes",
+    "adept_autotune_type_layouts",
     "adept_stats_get", "adept_dump_tracks", "adept_dump_ring", "adept_reset", "adept_autotune",
     "adept_set_timing", "adept_autotune_layout", "adept_last_error", "adept_destroy",
 ]
@@ -87,6 +88,9 @@ def lib():
         "adept_buffer_bytes": (i32, [P, P]),
         "adept_line_heat": (i32, [P, i32, u32, u32, P, sz]),
         "adept_layout_map": (i32, [Layout, i32, u64, u64, u64, P, P]),
+        "adept_create_typed": (i32, [P, i32, u64, P]),
+        "adept_type_buffer_bytes": (i32, [P, i32, P]),
+        "adept_autotune_type_layouts": (i32, [i32, u64, P, u32, u32, P, P, u64, P, P, P]),
         "adept_stats_get": (i32, [P, P]),
         "adept_dump_tracks": (i32, [P, i32, P, P, u64, P]),
         "adept_dump_ring": (i32, [P, i32, P, u64, P, P]),
@@ -125,6 +129,15 @@ def adept_create(scheme, mapping, precision, capacity, aosoa_lanes=64):
     h = ctypes.c_void_p()
     rc = lib().adept_create(Layout(scheme, mapping, aosoa_lanes), precision, int(capacity), ctypes.byref(h))
     _check(None, rc, "adept_create")
+    return h
+
+
+def adept_create_typed(scheme, layouts, precision, capacity):
+    """layouts: one (mapping, aosoa_lanes) per particle type (electron, positron, photon)."""
+    arr = (Layout * 3)(*[Layout(scheme, m, n) for m, n in layouts])
+    h = ctypes.c_void_p()
+    rc = lib().adept_create_typed(ctypes.cast(arr, ctypes.c_void_p), precision, int(capacity), ctypes.byref(h))
+    _check(None, rc, "adept_create_typed")
     return h
 
 
@@ -201,17 +214,23 @@ def adept_buffer_bytes(ctx):
     return n.value
 
 
+def adept_type_buffer_bytes(ctx, ptype):
+    n = ctypes.c_size_t()
+    _check(ctx, lib().adept_type_buffer_bytes(ctx, ptype, ctypes.byref(n)), "adept_type_buffer_bytes")
+    return n.value
+
+
 def adept_access_counts(ctx, ptype, buffer=0, heat=False):
     r = np.zeros(14, dtype=np.uint64)
     w = np.zeros(14, dtype=np.uint64)
-    hw = np.zeros(adept_buffer_bytes(ctx) // 4 if heat else 0, dtype=np.uint32)
+    hw = np.zeros(adept_type_buffer_bytes(ctx, ptype) // 4 if heat else 0, dtype=np.uint32)
     rc = lib().adept_access_counts(ctx, ptype, buffer, _ptr(r), _ptr(w), _ptr(hw) if heat else None, len(hw))
     _check(ctx, rc, "adept_access_counts")
     return (r, w, hw) if heat else (r, w)
 
 
 def adept_line_heat(ctx, ptype, buffer=0, line_bytes=128):
-    out = np.zeros(-(-adept_buffer_bytes(ctx) // line_bytes), dtype=np.uint64)
+    out = np.zeros(-(-adept_type_buffer_bytes(ctx, ptype) // line_bytes), dtype=np.uint64)
     _check(ctx, lib().adept_line_heat(ctx, ptype, buffer, line_bytes, _ptr(out), len(out)), "adept_line_heat")
     return out
 
@@ -297,6 +316,21 @@ def adept_autotune_layout(precision, capacity, candidates, seeds, primaries):
             {"block": l.block, "grid": l.grid, "graph_iters": l.graph_iters}, ms.value)
 
 
+def adept_autotune_type_layouts(precision, capacity, candidates, seeds, primaries):
+    """candidates: (scheme, mapping, aosoa_lanes) tuples of one scheme; returns
+    ([(mapping, aosoa_lanes)] * 3 per type, launch, ms)."""
+    arr = (Layout * len(candidates))(*[Layout(s, m, n) for s, m, n in candidates])
+    sd = np.ascontiguousarray(seeds, dtype=np.uint32)
+    p = np.ascontiguousarray(primaries).view(PRIMARY_DTYPE)
+    best, l, ms = (Layout * 3)(), Launch(), ctypes.c_double()
+    rc = lib().adept_autotune_type_layouts(precision, int(capacity), ctypes.cast(arr, ctypes.c_void_p),
+                                           len(candidates), len(sd), _ptr(sd), _ptr(p), len(p),
+                                           ctypes.cast(best, ctypes.c_void_p), ctypes.byref(l), ctypes.byref(ms))
+    _check(None, rc, "adept_autotune_type_layouts")
+    return ([(b.mapping, b.aosoa_lanes) for b in best],
+            {"block": l.block, "grid": l.grid, "graph_iters": l.graph_iters}, ms.value)
+
+
 def adept_last_error(ctx):
     return lib().adept_last_error(ctx).decode()
 
@@ -310,13 +344,19 @@ class Sim:
     """One context bound to a torch-owned device arena and torch's current stream."""
 
     def __init__(self, scheme=DENSE_DOUBLE, mapping=MAP_SOA, precision=MIXED, capacity=1 << 20, aosoa_lanes=64,
-                 seeds=(1,), scoring=None, admission=None, instrumented=None, launch=None, device="cuda"):
+                 seeds=(1,), scoring=None, admission=None, instrumented=None, launch=None, device="cuda",
+                 type_layouts=None):
+        """type_layouts: one (mapping, aosoa_lanes) per particle type (adept_create_typed);
+        mapping and aosoa_lanes are then ignored."""
         import torch
 
         self.scheme, self.mapping, self.precision, self.capacity = scheme, mapping, precision, int(capacity)
         self.n_events = len(seeds)
         self.nx = self.ny = 0
-        self.ctx = adept_create(scheme, mapping, precision, capacity, aosoa_lanes)
+        if type_layouts is not None:
+            self.ctx = adept_create_typed(scheme, type_layouts, precision, capacity)
+        else:
+            self.ctx = adept_create(scheme, mapping, precision, capacity, aosoa_lanes)
         try:
             adept_set_events(self.ctx, seeds)
             if scoring:

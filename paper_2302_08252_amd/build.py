@@ -15,7 +15,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libadept.so")
 ARCH = os.environ.get("ADEPT_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["capi.hip", "inst_dense_f64.hip", "inst_dense_mixed.hip", "inst_sparse_f64.hip", "inst_sparse_mixed.hip"]
+SOURCES = ["capi.hip", "inst_dense_f64.hip", "inst_dense_mixed.hip", "inst_sparse_f64.hip", "inst_sparse_mixed.hip",
+           "inst_typed.hip"]
 HEADERS = ["kernels.hpp", "layout.hpp", "model.hpp", os.path.join("..", "..", "include", "adept.h")]
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-munsafe-fp-atomics",

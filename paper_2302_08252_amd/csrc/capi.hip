@@ -252,7 +252,7 @@ __global__ void k_ctrl_init(const KArgs a) {
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-Ops g_ops[2][2][3][2];  // [scheme][precision][map][instr]
+Ops g_ops[2][2][4][2];  // [scheme][precision][map][instr]
 bool g_ops_ready = false;
 
 void init_ops() {
@@ -261,13 +261,16 @@ void init_ops() {
   ops_sparse_mixed(g_ops[SPARSE][1]);
   ops_dense_f64(g_ops[DENSE][0]);
   ops_dense_mixed(g_ops[DENSE][1]);
+  ops_typed(g_ops);
   g_ops_ready = true;
 }
 
 }  // namespace
 
 struct adept_ctx {
-  adept_layout layout{};
+  adept_layout layout{};  // the scheme; the mapping of every type unless typed
+  bool typed = false;     // one mapping per particle type (tlay)
+  adept_layout tlay[3]{};
   int prec = 0;
   unsigned long long C = 0;
   int state = CREATED;
@@ -292,7 +295,7 @@ struct adept_ctx {
   hipStream_t cap_stream = nullptr;
   HostMirror* mirror = nullptr;
   KArgs args{};
-  uint64_t buf_bytes = 0;
+  uint64_t buf_bytes[3] = {0, 0, 0};  // one physical track buffer of each type
   // staged primaries (library-owned device memory)
   adept_primary* staged = nullptr;
   unsigned long long staged_cap = 0;
@@ -343,9 +346,11 @@ size_t bump(size_t& at, size_t bytes) {
   return o;
 }
 
-uint64_t buf_bytes_of(const adept_ctx* c) {
-  return c->prec ? buffer_bytes<true>(c->layout.mapping, c->layout.aosoa_lanes, c->C)
-                 : buffer_bytes<false>(c->layout.mapping, c->layout.aosoa_lanes, c->C);
+const adept_layout& layout_of(const adept_ctx* c, int t) { return c->typed ? c->tlay[t] : c->layout; }
+
+uint64_t buf_bytes_of(const adept_ctx* c, int t) {
+  const adept_layout& l = layout_of(c, t);
+  return c->prec ? buffer_bytes<true>(l.mapping, l.aosoa_lanes, c->C) : buffer_bytes<false>(l.mapping, l.aosoa_lanes, c->C);
 }
 
 // Tally rows: the flat tally index space of one block (202 per event, then the
@@ -367,11 +372,10 @@ Plan plan(const adept_ctx* c) {
   Plan P{};
   size_t at = 0;
   const bool dense = c->layout.scheme == ADEPT_DENSE_DOUBLE;
-  const uint64_t bb = buf_bytes_of(c);
   const unsigned long long E = c->seeds.size();
   P.ctrl = bump(at, sizeof(Ctrl));
   for (int t = 0; t < 3; ++t)
-    for (int b = 0; b < 2; ++b) P.buf[t][b] = (b == 0 || dense) ? bump(at, bb) : 0;
+    for (int b = 0; b < 2; ++b) P.buf[t][b] = (b == 0 || dense) ? bump(at, buf_bytes_of(c, t)) : 0;
   for (int t = 0; t < 3; ++t) {
     for (int b = 0; b < 2; ++b) P.list[t][b] = dense ? 0 : bump(at, c->C * 4);
     P.ring[t] = dense ? 0 : bump(at, c->C * 4);
@@ -396,7 +400,7 @@ Plan plan(const adept_ctx* c) {
   P.fold = bump(at, P.fold_chunks * P.row_len * 8);
   P.rw = bump(at, 3 * 2 * 28 * 8);
   for (int t = 0; t < 3; ++t)
-    for (int b = 0; b < 2; ++b) P.heat[t][b] = (c->instr_on && (b == 0 || dense)) ? bump(at, bb) : 0;
+    for (int b = 0; b < 2; ++b) P.heat[t][b] = (c->instr_on && (b == 0 || dense)) ? bump(at, buf_bytes_of(c, t)) : 0;
   P.seeds = bump(at, E * 4);
   P.total = at;
   return P;
@@ -447,6 +451,11 @@ void fill_args(adept_ctx* c) {
   a.C = c->C;
   a.map = c->prec ? make_map_args<true>(c->layout.mapping, c->layout.aosoa_lanes, c->C)
                   : make_map_args<false>(c->layout.mapping, c->layout.aosoa_lanes, c->C);
+  for (int t = 0; t < 3; ++t) {
+    const adept_layout& l = layout_of(c, t);
+    a.tmap[t] = c->prec ? make_typed_args<true>(l.mapping, l.aosoa_lanes, c->C)
+                        : make_typed_args<false>(l.mapping, l.aosoa_lanes, c->C);
+  }
   a.instr_last = c->instr_last;
   a.instr_on = c->instr_on;
   a.adm_on = c->adm_on;
@@ -457,11 +466,11 @@ void fill_args(adept_ctx* c) {
   c->scratch = (double*)(A + P.scratch);
   c->fold = (double*)(A + P.fold);
   c->fold_chunks = (unsigned)P.fold_chunks;
-  c->buf_bytes = buf_bytes_of(c);
+  for (int t = 0; t < 3; ++t) c->buf_bytes[t] = buf_bytes_of(c, t);
 }
 
 const Ops& ops(const adept_ctx* c) {
-  return g_ops[c->layout.scheme][c->prec][c->layout.mapping][c->instr_on ? 1 : 0];
+  return g_ops[c->layout.scheme][c->prec][c->typed ? (int)MAP_TYPED : c->layout.mapping][c->instr_on ? 1 : 0];
 }
 
 unsigned grid_of(const adept_ctx* c) {
@@ -484,7 +493,7 @@ adept_status do_reset(adept_ctx* c) {
   HIPCHK(hipMemsetAsync((uint8_t*)c->arena + P.rw, 0, 3 * 2 * 28 * 8, c->stream));
   for (int t = 0; t < 3; ++t)
     for (int b = 0; b < 2; ++b)
-      if (a.heat[t][b]) HIPCHK(hipMemsetAsync(a.heat[t][b], 0, c->buf_bytes, c->stream));
+      if (a.heat[t][b]) HIPCHK(hipMemsetAsync(a.heat[t][b], 0, c->buf_bytes[t], c->stream));
   hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, c->stream, a);
   hipLaunchKernelGGL(k_reset, dim3(1024), dim3(256), 0, c->stream, a, 0ull, 0ull, 0ull, 0ull);
   HIPCHK(hipGetLastError());
@@ -680,25 +689,28 @@ int leaf_at(int map, const MapArgs& m, uint64_t lanes, uint64_t C, uint64_t b) {
 }
 }  // namespace
 
-// ---------------------------------------------------------------------------
-// ABI
-// ---------------------------------------------------------------------------
-extern "C" {
-
-adept_status adept_create(adept_layout layout, adept_precision precision, uint64_t capacity, adept_ctx** out) {
-  if (!out) return ADEPT_E_INVALID;
-  if (layout.scheme < 0 || layout.scheme > 1 || layout.mapping < 0 || layout.mapping > 2) return ADEPT_E_INVALID;
-  if (precision != ADEPT_FP64 && precision != ADEPT_MIXED) return ADEPT_E_INVALID;
-  if (capacity == 0 || capacity > (1ull << 30)) return ADEPT_E_INVALID;
+namespace {
+// Checks one layout (as adept_create documents) and normalises its lane count.
+bool valid_layout(adept_layout& layout, uint64_t capacity) {
+  if (layout.scheme < 0 || layout.scheme > 1 || layout.mapping < 0 || layout.mapping > 2) return false;
   if (layout.mapping == ADEPT_MAP_AOSOA) {
     const uint32_t N = layout.aosoa_lanes;
-    if (N < 2 || N > 256 || (N & (N - 1)) || capacity % N) return ADEPT_E_INVALID;
+    if (N < 2 || N > 256 || (N & (N - 1)) || capacity % N) return false;
   } else {
     layout.aosoa_lanes = 1;
   }
+  return true;
+}
+
+adept_status create_ctx(adept_layout layout, const adept_layout* typed, adept_precision precision, uint64_t capacity,
+                        adept_ctx** out) {
   init_ops();
   adept_ctx* c = new adept_ctx();
   c->layout = layout;
+  if (typed) {
+    c->typed = true;
+    for (int t = 0; t < 3; ++t) c->tlay[t] = typed[t];
+  }
   c->prec = precision;
   c->C = capacity;
   if (hipGetDevice(&c->device) != hipSuccess ||
@@ -712,6 +724,66 @@ adept_status adept_create(adept_layout layout, adept_precision precision, uint64
   memset(c->mirror, 0, sizeof(HostMirror));
   *out = c;
   return ADEPT_OK;
+}
+}  // namespace
+
+namespace {
+// Best of three timed runs of the given per-type layouts (a scratch context);
+// the launch is tuned first when `tune` is set, else taken from *launch.
+adept_status time_typed(const adept_layout lay[3], adept_precision precision, uint64_t capacity, uint32_t n_events,
+                        const uint32_t* seeds, const adept_primary* p, uint64_t n, bool tune, adept_launch* launch,
+                        float* ms) {
+  adept_ctx* c = nullptr;
+  adept_status rc = adept_create_typed(lay, precision, capacity, &c);
+  if (rc) return rc;
+  rc = adept_set_events(c, n_events, seeds);
+  if (!rc) rc = tune ? adept_autotune(c, p, n, launch) : adept_set_launch(c, launch);
+  *ms = 1e30f;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) rc = ADEPT_E_DEVICE;
+  for (int rep = 0; rep < 3 && !rc; ++rep) {
+    rc = adept_reset(c);
+    if (!rc) rc = adept_inject(c, p, n);
+    if (!rc) (void)hipEventRecord(e0, c->stream);
+    uint64_t it = 0;
+    if (!rc) rc = adept_run(c, ~0ull, &it);
+    if (!rc) {
+      float t = 0.f;
+      (void)hipEventRecord(e1, c->stream);
+      (void)hipEventSynchronize(e1);
+      (void)hipEventElapsedTime(&t, e0, e1);
+      *ms = std::min(*ms, t);
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  adept_destroy(c);
+  return rc;
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+adept_status adept_create(adept_layout layout, adept_precision precision, uint64_t capacity, adept_ctx** out) {
+  if (!out) return ADEPT_E_INVALID;
+  if (precision != ADEPT_FP64 && precision != ADEPT_MIXED) return ADEPT_E_INVALID;
+  if (capacity == 0 || capacity > (1ull << 30)) return ADEPT_E_INVALID;
+  if (!valid_layout(layout, capacity)) return ADEPT_E_INVALID;
+  return create_ctx(layout, nullptr, precision, capacity, out);
+}
+
+adept_status adept_create_typed(const adept_layout layouts[3], adept_precision precision, uint64_t capacity,
+                                adept_ctx** out) {
+  if (!out || !layouts) return ADEPT_E_INVALID;
+  if (precision != ADEPT_FP64 && precision != ADEPT_MIXED) return ADEPT_E_INVALID;
+  if (capacity == 0 || capacity > (1ull << 30)) return ADEPT_E_INVALID;
+  adept_layout l[3] = {layouts[0], layouts[1], layouts[2]};
+  for (int t = 0; t < 3; ++t)
+    if (!valid_layout(l[t], capacity) || l[t].scheme != l[0].scheme) return ADEPT_E_INVALID;
+  return create_ctx(l[0], l, precision, capacity, out);
 }
 
 adept_status adept_arena_bytes(const adept_ctx* c, size_t* bytes) {
@@ -942,8 +1014,14 @@ adept_status adept_tally(adept_ctx* c, adept_tally_kind kind, double* out, size_
 }
 
 adept_status adept_buffer_bytes(const adept_ctx* c, size_t* bytes) {
-  if (!c || !bytes) return ADEPT_E_INVALID;
-  *bytes = buf_bytes_of(c);
+  if (!c || !bytes || c->typed) return ADEPT_E_INVALID;
+  *bytes = buf_bytes_of(c, 0);
+  return ADEPT_OK;
+}
+
+adept_status adept_type_buffer_bytes(const adept_ctx* c, adept_particle t, size_t* bytes) {
+  if (!c || !bytes || t < 0 || t > 2) return ADEPT_E_INVALID;
+  *bytes = buf_bytes_of(c, t);
   return ADEPT_OK;
 }
 
@@ -961,7 +1039,7 @@ adept_status adept_access_counts(adept_ctx* c, adept_particle t, uint32_t buffer
     if (writes) writes[l] = rw[2 * l + 1];
   }
   if (heat_words) {
-    if (n_words * 4 != c->buf_bytes) return fail(c, ADEPT_E_INVALID, "n_words must be buffer bytes / 4");
+    if (n_words * 4 != c->buf_bytes[t]) return fail(c, ADEPT_E_INVALID, "n_words must be buffer bytes / 4");
     if (!a.heat[t][buffer]) {
       memset(heat_words, 0, n_words * 4);
     } else {
@@ -978,12 +1056,12 @@ adept_status adept_line_heat(adept_ctx* c, adept_particle t, uint32_t buffer, ui
   if (c->state == CREATED) return fail(c, ADEPT_E_STATE, "no state yet");
   const KArgs& a = c->args;
   if (!a.heat[t][buffer]) return fail(c, ADEPT_E_STATE, "not instrumented");
-  const unsigned long long lines = (c->buf_bytes + line_bytes - 1) / line_bytes;
+  const unsigned long long lines = (c->buf_bytes[t] + line_bytes - 1) / line_bytes;
   if (n_lines != lines) return fail(c, ADEPT_E_INVALID, "n_lines must be ceil(buffer bytes / line_bytes)");
   unsigned long long* d = nullptr;
   HIPCHK(hipMalloc(&d, lines * 8));
   hipLaunchKernelGGL(k_line_heat, dim3((unsigned)((lines + 255) / 256)), dim3(256), 0, c->stream, a.heat[t][buffer],
-                     (unsigned long long)(c->buf_bytes / 4), line_bytes / 4, d, lines);
+                     (unsigned long long)(c->buf_bytes[t] / 4), line_bytes / 4, d, lines);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipMemcpyAsync(out, d, lines * 8, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -1194,6 +1272,55 @@ adept_status adept_autotune_layout(adept_precision precision, uint64_t capacity,
   *best_layout = candidates[best_i];
   if (best_launch) *best_launch = best_l;
   if (best_ms) *best_ms = best;
+  return ADEPT_OK;
+}
+
+adept_status adept_autotune_type_layouts(adept_precision precision, uint64_t capacity, const adept_layout* candidates,
+                                         uint32_t n_candidates, uint32_t n_events, const uint32_t* seeds,
+                                         const adept_primary* p, uint64_t n, adept_layout best[3],
+                                         adept_launch* best_launch, double* best_ms) {
+  if (!candidates || n_candidates == 0 || !seeds || n_events == 0 || (!p && n) || !best) return ADEPT_E_INVALID;
+  for (uint32_t i = 0; i < n_candidates; ++i) {
+    adept_layout l = candidates[i];
+    if (!valid_layout(l, capacity) || l.scheme != candidates[0].scheme) return ADEPT_E_INVALID;
+  }
+  // the best shared layout, each with its tuned launch
+  adept_layout cur[3];
+  adept_launch launch{};
+  float cur_ms = 1e30f;
+  for (uint32_t i = 0; i < n_candidates; ++i) {
+    const adept_layout lay[3] = {candidates[i], candidates[i], candidates[i]};
+    adept_launch l{};
+    float ms = 0.f;
+    const adept_status rc = time_typed(lay, precision, capacity, n_events, seeds, p, n, true, &l, &ms);
+    if (rc) return rc;
+    if (ms < cur_ms * 0.98f) {
+      cur_ms = ms;
+      launch = l;
+      for (int t = 0; t < 3; ++t) cur[t] = candidates[i];
+    }
+  }
+  // then one pass over the types: a type moves to another candidate if the
+  // whole run gets more than 2% faster with that launch
+  for (int t = 0; t < 3; ++t) {
+    for (uint32_t i = 0; i < n_candidates; ++i) {
+      adept_layout lay[3] = {cur[0], cur[1], cur[2]};
+      lay[t] = candidates[i];
+      if (lay[t].mapping == cur[t].mapping &&
+          (lay[t].mapping != ADEPT_MAP_AOSOA || lay[t].aosoa_lanes == cur[t].aosoa_lanes))
+        continue;
+      float ms = 0.f;
+      const adept_status rc = time_typed(lay, precision, capacity, n_events, seeds, p, n, false, &launch, &ms);
+      if (rc) return rc;
+      if (ms < cur_ms * 0.98f) {
+        cur_ms = ms;
+        cur[t] = lay[t];
+      }
+    }
+  }
+  for (int t = 0; t < 3; ++t) best[t] = cur[t];
+  if (best_launch) *best_launch = launch;
+  if (best_ms) *best_ms = cur_ms;
   return ADEPT_OK;
 }
 

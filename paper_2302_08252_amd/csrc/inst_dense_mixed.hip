@@ -3,7 +3,7 @@
 #include "kernels.hpp"
 
 namespace adept {
-void ops_dense_mixed(Ops t[3][2]) {
+void ops_dense_mixed(Ops t[4][2]) {
   t[MAP_AOS][0] = Variant<DENSE, MAP_AOS, PolicyMixed, false>::ops();
   t[MAP_AOS][1] = Variant<DENSE, MAP_AOS, PolicyMixed, true>::ops();
   t[MAP_SOA][0] = Variant<DENSE, MAP_SOA, PolicyMixed, false>::ops();

@@ -3,7 +3,7 @@
 #include "kernels.hpp"
 
 namespace adept {
-void ops_sparse_f64(Ops t[3][2]) {
+void ops_sparse_f64(Ops t[4][2]) {
   t[MAP_AOS][0] = Variant<SPARSE, MAP_AOS, PolicyF64, false>::ops();
   t[MAP_AOS][1] = Variant<SPARSE, MAP_AOS, PolicyF64, true>::ops();
   t[MAP_SOA][0] = Variant<SPARSE, MAP_SOA, PolicyF64, false>::ops();

@@ -3,7 +3,7 @@
 #include "kernels.hpp"
 
 namespace adept {
-void ops_sparse_mixed(Ops t[3][2]) {
+void ops_sparse_mixed(Ops t[4][2]) {
   t[MAP_AOS][0] = Variant<SPARSE, MAP_AOS, PolicyMixed, false>::ops();
   t[MAP_AOS][1] = Variant<SPARSE, MAP_AOS, PolicyMixed, true>::ops();
   t[MAP_SOA][0] = Variant<SPARSE, MAP_SOA, PolicyMixed, false>::ops();

@@ -117,6 +117,7 @@ struct KArgs {
   int scheme;
   unsigned long long C;
   MapArgs map;
+  MapArgs tmap[3];             // per particle type (mapping MAP_TYPED)
   // instrumentation
   unsigned long long* rw[3][2];
   uint32_t* heat[3][2];
@@ -575,7 +576,8 @@ template <int MAP, class P, bool INSTR>
 __device__ __forceinline__ Acc<MAP, P::mixed, INSTR> make_acc(const KArgs& a, int type, int b, bool on) {
   Acc<MAP, P::mixed, INSTR> A;
   A.base = a.buf[type][b];
-  A.m = a.map;
+  if constexpr (MAP == MAP_TYPED) A.m = a.tmap[type];
+  else A.m = a.map;
   A.in.rw = a.rw[type][b];
   A.in.heat = a.heat[type][b];
   A.on = on;
@@ -1131,9 +1133,10 @@ struct Variant {
 };
 
 // ops_<scheme>_<precision>(table[map][instr]) are defined one per translation unit.
-void ops_sparse_f64(Ops t[3][2]);
-void ops_sparse_mixed(Ops t[3][2]);
-void ops_dense_f64(Ops t[3][2]);
-void ops_dense_mixed(Ops t[3][2]);
+void ops_sparse_f64(Ops t[4][2]);
+void ops_sparse_mixed(Ops t[4][2]);
+void ops_dense_f64(Ops t[4][2]);
+void ops_dense_mixed(Ops t[4][2]);
+void ops_typed(Ops t[2][2][4][2]);  // the per-type mapping of both schemes and precisions
 
 }  // namespace adept

@@ -13,6 +13,11 @@
 //   AoSoA-N  addr = (slot / N) * N * R + N * prefix(leaf) + (slot % N) * size(leaf),
 //            N a power of two in [2, 256], R the unpadded record size
 //            (paper Sec. 4: fields (A,B,C) with N = 2 are laid out AABBCCAABBCC)
+//   per type one of the three above for each particle type's buffers (the per-
+//            particle-type layouts proposed as future work in paper Sec. 6), all
+//            written as addr = (slot >> g) * B + F(leaf) + (slot & (2^g - 1)) * size(leaf):
+//            AoS g = 0, B = stride, F = offset; SoA g = 63, F = start;
+//            AoSoA-N g = log2 N, B = N * R, F = N * prefix
 //
 // The accessor routes every field load and store through the mapping; its
 // instrumented form (paper Sec. 5) counts reads and writes per field (one
@@ -31,7 +36,7 @@
 
 namespace adept {
 
-enum : int { MAP_AOS = 0, MAP_SOA = 1, MAP_AOSOA = 2 };
+enum : int { MAP_AOS = 0, MAP_SOA = 1, MAP_AOSOA = 2, MAP_TYPED = 3 };
 enum : int { SPARSE = 0, DENSE = 1 };
 
 template <bool MIXED>
@@ -63,9 +68,10 @@ struct Rec<true> {
 
 // Runtime parameters of one mapping instance (host-computed, passed by value).
 struct MapArgs {
-  uint64_t soa_start[14];  // SoA: byte offset of each field array
-  uint32_t lg;             // AoSoA: log2 N
+  uint64_t soa_start[14];  // SoA: byte offset of each field array; per type: F(leaf)
+  uint32_t lg;             // AoSoA: log2 N; per type: g
   uint32_t pad;
+  uint64_t blk;            // per type: B
 };
 
 __host__ __device__ inline uint64_t align256(uint64_t x) { return (x + 255u) & ~(uint64_t)255u; }
@@ -81,6 +87,25 @@ inline MapArgs make_map_args(int map, uint32_t lanes, uint64_t C) {
   uint32_t lg = 0;
   while ((1u << lg) < lanes) ++lg;
   m.lg = map == MAP_AOSOA ? lg : 0;
+  return m;
+}
+
+// The per-type form of mapping `map` (AoS, SoA or AoSoA with `lanes` lanes).
+template <bool MIXED>
+inline MapArgs make_typed_args(int map, uint32_t lanes, uint64_t C) {
+  using RC = Rec<MIXED>;
+  MapArgs m = make_map_args<MIXED>(map, lanes, C);
+  if (map == MAP_AOS) {
+    m.lg = 0;
+    m.blk = RC::stride;
+    for (int l = 0; l < 14; ++l) m.soa_start[l] = RC::off(l);
+  } else if (map == MAP_SOA) {
+    m.lg = 63;
+    m.blk = 0;
+  } else {
+    m.blk = (uint64_t)lanes * RC::bytes;
+    for (int l = 0; l < 14; ++l) m.soa_start[l] = (uint64_t)RC::prefix(l) << m.lg;
+  }
   return m;
 }
 
@@ -101,6 +126,8 @@ __host__ __device__ __forceinline__ uint64_t leaf_addr(const MapArgs& m, uint64_
   using RC = Rec<MIXED>;
   if (MAP == MAP_AOS) return slot * RC::stride + RC::off(l);
   if (MAP == MAP_SOA) return m.soa_start[l] + slot * RC::size(l);
+  if (MAP == MAP_TYPED)
+    return (slot >> m.lg) * m.blk + m.soa_start[l] + (slot & ((1ull << m.lg) - 1)) * RC::size(l);
   const uint64_t mask = (1ull << m.lg) - 1;
   return (slot & ~mask) * RC::bytes + ((uint64_t)RC::prefix(l) << m.lg) + (slot & mask) * RC::size(l);
 }

@@ -107,3 +107,27 @@ def test_layout_map_rejects_bad_arguments():
     assert L.adept_layout_map(ad.Layout(0, 0, 1), 0, 0, 0, 8, p, None) == ad.E_INVALID
     assert L.adept_layout_map(ad.Layout(0, 0, 1), 0, 96, 0, 8, None, None) == ad.E_INVALID
     assert L.adept_layout_map(ad.Layout(0, 0, 1), 0, 96, 0, 0, None, None) == ad.OK
+
+
+def test_create_typed_rejects_bad_arguments():
+    """Per-type layouts: each is checked as adept_create checks one, and all three
+    must name the same scheme."""
+    import paper_2302_08252_amd as ad
+
+    if not os.path.exists(ad.LIB_PATH):
+        pytest.skip("libadept.so not built")
+    L = ad.lib()
+    h = ctypes.c_void_p()
+
+    def typed(*lays, cap=1024, prec=0):
+        arr = (ad.Layout * 3)(*lays)
+        return L.adept_create_typed(ctypes.cast(arr, ctypes.c_void_p), prec, cap, ctypes.byref(h))
+
+    assert typed(ad.Layout(1, 0, 1), ad.Layout(0, 1, 1), ad.Layout(1, 2, 64)) == ad.E_INVALID  # schemes differ
+    assert typed(ad.Layout(1, 0, 1), ad.Layout(1, 2, 3), ad.Layout(1, 1, 1)) == ad.E_INVALID  # lanes not a power of 2
+    assert typed(ad.Layout(1, 0, 1), ad.Layout(1, 2, 64), ad.Layout(1, 1, 1), cap=1000) == ad.E_INVALID
+    assert typed(ad.Layout(1, 0, 1), ad.Layout(1, 4, 1), ad.Layout(1, 1, 1)) == ad.E_INVALID
+    assert typed(ad.Layout(1, 0, 1), ad.Layout(1, 1, 1), ad.Layout(1, 1, 1), prec=5) == ad.E_INVALID
+    assert L.adept_create_typed(None, 0, 1024, ctypes.byref(h)) == ad.E_INVALID
+    n = ctypes.c_size_t()
+    assert L.adept_type_buffer_bytes(None, 0, ctypes.byref(n)) == ad.E_INVALID
