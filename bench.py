@@ -75,7 +75,7 @@ def parse():
     ap.add_argument("--graph-iters", type=int, default=32)
     ap.add_argument("--fp64-steps", type=int, default=2, help="timed runs of each FP64 comparison path (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=4800, help="primaries of the workload run by the oracle")
+    ap.add_argument("--cpu-sample", type=int, default=9600, help="primaries of the workload run by the oracle")
     ap.add_argument("--headline-only", action="store_true", help="only the headline path (for profilers)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched uneven-events section")
     ap.add_argument("--per-event-sample", type=int, default=32, help="events timed one launch sequence each")
@@ -170,9 +170,15 @@ def cpu_baseline(wl, sample, precision):
     with mp.get_context("fork").Pool(len(args)) as pool:
         steps = pool.map(_oracle_chunk, args)
     dt = time.perf_counter() - t0
+    # one core on a twentieth of the sample, for the per-core rate
+    t1 = time.perf_counter()
+    steps1 = _oracle_chunk((prims[:max(1, sample // 20)], wl.seeds, precision))
+    dt1 = time.perf_counter() - t1
     return {"value": sum(steps) / dt, "unit": "track-steps/s", "cores": len(args), "kind": "oracle",
             "sample": f"first {sample} primaries of the workload, dense double buffer, "
-                      f"{'mixed' if precision else 'FP64'} policy, {sum(steps)} track-steps in {dt:.2f} s wall"}
+                      f"{'mixed' if precision else 'FP64'} policy, {sum(steps)} track-steps in {dt:.2f} s wall",
+            "single_core": {"value": steps1 / dt1, "sample": f"first {max(1, sample // 20)} primaries, "
+                                                              f"{steps1} track-steps in {dt1:.2f} s"}}
 
 
 def _oracle_chunk(a):
