@@ -717,13 +717,11 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
   if (threadIdx.x == 0) ss.waves = ss.waves_div = ss.surv[0] = ss.surv[1] = ss.surv[2] = 0;
   __syncthreads();
   const int lane = __lane_id();
-  // The next tile's ticket is taken once this tile's look-back is done, so the
-  // atomic overlaps the stores of the write phase.  (Taking it any earlier
-  // would make every later tile's look-back wait for this block.)
+  // Tiles are claimed in ticket order when a block is ready to start one, so
+  // that a tile's predecessors are as far along as it is.
   if (threadIdx.x == 0)
     sh.ticket = __hip_atomic_fetch_add(&c->ticket[p], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
-  unsigned long long my_next = 0;
   for (;;) {
     const unsigned long long tile = sh.ticket;
     if (tile >= total) break;
@@ -815,8 +813,6 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
     __syncthreads();
     if (tile == total - 1 && threadIdx.x < NV)
       c->tot[p][threadIdx.x] = sat_add(sh.tile_excl[threadIdx.x], sh.tile_agg[threadIdx.x]);
-    if (threadIdx.x == 0)
-      my_next = __hip_atomic_fetch_add(&c->ticket[p], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
     // Writes of one track u of this lane: survivor, kill, creations.
     auto emit = [&](int u, const Track<R>& t, const Creations<R>& cr, bool surv, uint64_t aux) {
@@ -899,9 +895,12 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
         if (valid) emit(u, t, cr, surv, aux);
       }
     }
-    // Every read of this tile's LDS state is done; the next tile's ticket is
-    // published before the one barrier that separates the two tiles.
-    if (threadIdx.x == 0) sh.ticket = my_next;
+    // Every read of this tile's LDS state is done.  The next ticket is taken only
+    // now, when the block can start on it at once: a tile claimed while its block
+    // is still writing holds up the look-back of every later tile.
+    __syncthreads();
+    if (threadIdx.x == 0)
+      sh.ticket = __hip_atomic_fetch_add(&c->ticket[p], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
   }
   if (lds_tally) flush(a, tl);
