@@ -364,3 +364,33 @@ def test_layout_autotuner_keeps_results(ad, oracle_mod):
     o.run()
     compare_tallies(sim, o, oracle_mod)
     sim.close()
+
+
+def test_timed_mode_keeps_results(ad, oracle_mod):
+    """Timed mode (iterations launched one by one with an event pair around every step
+    kernel, in chunks of graph_iters) gives the untimed results; every step launch is
+    timed and the summed kernel time fits inside the wall time of the run."""
+    import time
+
+    import torch
+
+    say("case timed_mode")
+    wl = workloads.cfg0()
+    sim = ad.Sim(1, 1, 1, 1 << 16, seeds=wl.seeds, launch={"block": 1024, "graph_iters": 16})
+    sim.inject(wl.primaries)
+    ref_it = sim.run()
+    ref = sim.tally(oracle_mod.T_LAYER)
+    sim.reset()
+    ad.adept_set_timing(sim.ctx, True)
+    sim.inject(wl.primaries)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it = sim.run(5)  # a partial chunk
+    it += sim.run()
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    st = sim.stats()
+    assert it == ref_it and np.array_equal(sim.tally(oracle_mod.T_LAYER), ref)
+    assert st["step_launches"] == 5 + -(-(ref_it - 5) // 16) * 16
+    assert 0 < st["step_kernel_ms"] < wall_ms
+    sim.close()
