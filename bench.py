@@ -22,7 +22,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, AMD's published figure
 KERNEL_SOURCES = ["kernels.hpp", "layout.hpp", "model.hpp", "inst_dense_mixed.hip"]
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_step_cfg2_dense_soa_mixed_pmc.md")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_step_100ke_10gev_dense_soa_mixed_pmc.md")
 
 
 def kernel_source_hash():
@@ -79,9 +79,9 @@ def parse():
     ap.add_argument("--headline-only", action="store_true", help="only the headline path (for profilers)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched uneven-events section")
     ap.add_argument("--per-event-sample", type=int, default=32, help="events timed one launch sequence each")
-    ap.add_argument("--cfg4", action="store_true", help="also run 10^6 e- in 1000 events with 500k cells")
+    ap.add_argument("--segmented", action="store_true", help="also run 10^6 e- in 1000 events with 500k cells")
     ap.add_argument("--layout-study", action="store_true",
-                    help="also time cfg1 in the paper's four layouts and summarise its access counts")
+                    help="also time showers_10ke_10gev in the paper's four layouts and summarise its access counts")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device to device (a plain copy of known size for scaling counters)")
     return ap.parse_args()
@@ -192,8 +192,8 @@ def _oracle_chunk(a):
     return sum(o.stats()["track_steps"])
 
 
-def kappa_cfg1():
-    path = os.path.join(ROOT, "tests", "golden", "kappa_cfg1.txt")
+def kappa_per_gev():
+    path = os.path.join(ROOT, "tests", "golden", "kappa_per_gev.txt")
     line = [l for l in open(path) if not l.startswith("#")][0]
     return [float(x) for x in line.split()]
 
@@ -217,10 +217,10 @@ def run_once(ad, torch, sim, prims=None, dev=None):
 
 
 def batched_section(ad, torch, np, workloads, args):
-    """512 uneven events (cfg3): layout and launch picked by the autotuner on a
+    """512 uneven events (uneven_512_events): layout and launch picked by the autotuner on a
     64-event sample, events admitted by the capacity rule, per-event tallies."""
-    wl = workloads.cfg3()
-    kappa = kappa_cfg1()
+    wl = workloads.uneven_512_events()
+    kappa = kappa_per_gev()
     C = 1 << 24
     cands = [(1, 0, 1), (1, 1, 1), (1, 2, 16), (1, 2, 64), (1, 2, 256)]
     sample = wl.primaries[wl.primaries["event"] < 64]  # ~64k primaries: peak below 1e7 photons < 2^24
@@ -261,10 +261,10 @@ def batched_section(ad, torch, np, workloads, args):
     return out
 
 
-def cfg4_section(ad, torch, np, workloads):
-    wl = workloads.cfg4()
+def segmented_section(ad, torch, np, workloads):
+    wl = workloads.segmented_1000_events()
     C = 1 << 28
-    kappa = kappa_cfg1()
+    kappa = kappa_per_gev()
     sim = ad.Sim(ad.DENSE_DOUBLE, ad.MAP_SOA, ad.MIXED, C, 64, seeds=wl.seeds, scoring=(100, 100, 4.0),
                  admission=(0.8, kappa), launch={"block": 1024, "graph_iters": 32})
     ad.adept_set_timing(sim.ctx, True)
@@ -287,7 +287,7 @@ def layout_study(ad, torch, np, workloads):
     single buffer (AoS) and the dense double buffer (AoS, SoA, AoSoA-64); then, in
     instrumented mode over injection + 20 iterations, the per-field access counts of
     the electron buffer, slot utilisation and the per-type maximum access counts."""
-    wl = workloads.cfg1()
+    wl = workloads.showers_10ke_10gev()
     C = 1 << 22
     dev = torch.from_numpy(wl.primaries.view(np.uint8).copy()).cuda()
     res = {"workload": wl.description, "precision": "FP64", "timings": {}}
@@ -380,7 +380,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    wl = workloads.cfg2(args.primaries)
+    wl = workloads.showers_100ke_10gev(args.primaries)
     C = 1 << args.capacity_log2
     dev_prims = torch.from_numpy(wl.primaries.view(np.uint8).copy()).cuda()
     head = time_path(ad, torch, wl, dev_prims, ad.DENSE_DOUBLE, ad.MAP_SOA, ad.MIXED, C, args, args.steps,
@@ -445,11 +445,11 @@ def main():
             "reference": "the same workload in FP64 on the GPU (bit-exact with the FP64 oracle per track)",
         }
     if not args.headline_only and not args.no_batched:
-        out["batched_cfg3"] = batched_section(ad, torch, np, workloads, args)
-    if args.cfg4:
-        out["cfg4"] = cfg4_section(ad, torch, np, workloads)
+        out["batched_512_events"] = batched_section(ad, torch, np, workloads, args)
+    if args.segmented:
+        out["segmented_1000_events"] = segmented_section(ad, torch, np, workloads)
     if args.layout_study:
-        out["layout_study_cfg1"] = layout_study(ad, torch, np, workloads)
+        out["layout_study_10ke"] = layout_study(ad, torch, np, workloads)
     if not args.headline_only and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample, 1)
     print(json.dumps(out), flush=True)

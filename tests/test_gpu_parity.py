@@ -102,11 +102,11 @@ def test_iterations_bitwise(ad, oracle_mod, scheme, mapping, lanes, precision, b
 
 
 @pytest.mark.parametrize("block", [64, 128, 256, 512, 1024])
-def test_cfg0_run_graph(ad, oracle_mod, block):
-    """cfg0 as specified (sparse AoS FP64, 2^20 slots, 100 e- of 1 GeV, seed 1) through
+def test_anchor_run_graph(ad, oracle_mod, block):
+    """showers_100e_1gev as specified (sparse AoS FP64, 2^20 slots, 100 e- of 1 GeV, seed 1) through
     adept_run's graph replay: counts and stats exact, per-layer deposits 1e-12."""
-    say(f"case cfg0_run_graph block={block}")
-    wl = workloads.cfg0()
+    say(f"case anchor_run_graph block={block}")
+    wl = workloads.showers_100e_1gev()
     sim = ad.Sim(0, 0, 0, 1 << 20, 1, seeds=wl.seeds, launch={"block": block, "graph_iters": 32})
     sim.inject(wl.primaries)
     it = sim.run()
@@ -220,7 +220,7 @@ def test_batched_admission_and_cells(ad, oracle_mod, precision, hold, block):
     tally rows (the rest add to the tallies directly); 512 and 1024 run tiles of
     two tracks per lane under the mixed policy."""
     say(f"case batched precision={precision} hold={hold} block={block}")
-    wl = workloads.cfg3(n_events=24, max_per_event=6)
+    wl = workloads.uneven_512_events(n_events=24, max_per_event=6)
     kappa = [3.0, 2.0, 25.0]
     C = 1 << 14  # tight enough that admission staggers the events for hold > 0
     sim = ad.Sim(1, 1, precision, C, 1, seeds=wl.seeds, scoring=(100, 100, 4.0), admission=(0.8, kappa, hold),
@@ -248,7 +248,7 @@ def test_batched_admission_and_cells(ad, oracle_mod, precision, hold, block):
 
 def test_determinism_and_launch_invariance(ad, oracle_mod):
     say("case determinism")
-    wl = workloads.cfg0().subset(20)
+    wl = workloads.showers_100e_1gev().subset(20)
     res = []
     for block, k in ((64, 4), (256, 32), (128, 1)):
         sim = ad.Sim(1, 2, 1, 1 << 16, 32, seeds=wl.seeds, launch={"block": block, "graph_iters": k})
@@ -267,7 +267,7 @@ def test_full_size_one_iteration(ad, oracle_mod, precision, scheme, mapping):
     next states must agree track for track (and slot for slot); the deposits of that
     iteration agree to 1e-12 of the layer totals."""
     say(f"case full_size precision={precision} scheme={scheme} mapping={mapping}")
-    wl = workloads.cfg2()
+    wl = workloads.showers_100ke_10gev()
     C = 1 << 25
     sim = ad.Sim(scheme, mapping, precision, C, 64, seeds=wl.seeds, launch={"block": 256, "graph_iters": 32})
     sim.inject(wl.primaries)
@@ -295,13 +295,13 @@ def test_full_size_one_iteration(ad, oracle_mod, precision, scheme, mapping):
     sim.close()
 
 
-def test_cfg1_layout_study_counts_full_size(ad, oracle_mod):
+def test_layout_study_counts_full_size(ad, oracle_mod):
     """The layout study at full size: 10^4 e- of 10 GeV (seed 1), instrumented over
     injection + the first 20 iterations, in sparse AoS and dense AoS / SoA / AoSoA-64
     (FP64).  Per-field read/write totals and per-word heatmaps bit-exact; the per-field
     totals are the same for every layout of one scheme."""
-    say("case cfg1 layout study, full size")
-    wl = workloads.cfg1()
+    say("case showers_10ke_10gev layout study, full size")
+    wl = workloads.showers_10ke_10gev()
     C = 1 << 22
     for scheme, layouts in ((0, [(0, 1)]), (1, [(0, 1), (1, 1), (2, 64)])):
         o = oracle_mod.Oracle(scheme, 0, C, wl.seeds)
@@ -330,7 +330,7 @@ def test_autotune_keeps_results(ad, oracle_mod):
     """The autotuner only changes the launch configuration: the run it leaves behind
     reproduces the oracle's counts and deposits."""
     say("case autotune")
-    wl = workloads.cfg3(n_events=16, max_per_event=20)
+    wl = workloads.uneven_512_events(n_events=16, max_per_event=20)
     C = 1 << 16
     sim = ad.Sim(1, 1, 1, C, 1, seeds=wl.seeds)
     choice = ad.adept_autotune(sim.ctx, wl.primaries)
@@ -348,7 +348,7 @@ def test_layout_autotuner_keeps_results(ad, oracle_mod):
     """adept_autotune_layout picks one of the candidate layouts; a run in the chosen
     layout and launch configuration reproduces the oracle's state and deposits."""
     say("case layout autotuner")
-    wl = workloads.cfg3(n_events=8, max_per_event=12)
+    wl = workloads.uneven_512_events(n_events=8, max_per_event=12)
     cands = [(1, 0, 1), (1, 1, 1), (1, 2, 64), (0, 0, 1)]
     C = 1 << 16
     layout, launch, ms = ad.adept_autotune_layout(ad.MIXED, C, cands, wl.seeds, wl.primaries)
@@ -375,7 +375,7 @@ def test_timed_mode_keeps_results(ad, oracle_mod):
     import torch
 
     say("case timed_mode")
-    wl = workloads.cfg0()
+    wl = workloads.showers_100e_1gev()
     sim = ad.Sim(1, 1, 1, 1 << 16, seeds=wl.seeds, launch={"block": 1024, "graph_iters": 16})
     sim.inject(wl.primaries)
     ref_it = sim.run()

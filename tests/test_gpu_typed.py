@@ -86,7 +86,7 @@ def test_typed_autotuner_keeps_results(ad, oracle_mod):
     """The per-type autotuner on a small sample returns valid layouts; a run with its
     choice gives the oracle's counts and tallies."""
     say("case typed_autotuner")
-    wl = workloads.cfg0()
+    wl = workloads.showers_100e_1gev()
     cands = [(1, 0, 1), (1, 1, 1), (1, 2, 64)]
     lay, launch, ms = ad.adept_autotune_type_layouts(ad.MIXED, 1 << 16, cands, wl.seeds, wl.primaries)
     assert ms > 0 and all(l in [(m, n) for _, m, n in cands] for l in lay), lay

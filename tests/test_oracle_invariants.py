@@ -60,7 +60,7 @@ def test_energy_closure(oracle_mod, scheme, precision):
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_dense_and_sparse_agree(oracle_mod, precision):
-    wl = workloads.cfg0().subset(10)
+    wl = workloads.showers_100e_1gev().subset(10)
     od = oracle_mod.Oracle(oracle_mod.DENSE, precision, 1 << 14, wl.seeds)
     os_ = oracle_mod.Oracle(oracle_mod.SPARSE, precision, 1 << 14, wl.seeds)
     assert od.inject(wl.primaries) == 0 and os_.inject(wl.primaries) == 0
@@ -220,7 +220,7 @@ def test_counts_stop_after_window(oracle_mod):
 
 
 def test_mixed_policy_flips_are_rare(oracle_mod):
-    wl = workloads.cfg0().subset(50)
+    wl = workloads.showers_100e_1gev().subset(50)
     a = oracle_mod.Oracle(oracle_mod.DENSE, 0, 1 << 16, wl.seeds)
     b = oracle_mod.Oracle(oracle_mod.DENSE, 1, 1 << 16, wl.seeds)
     a.inject(wl.primaries)
@@ -261,7 +261,7 @@ def test_cell_scoring_closed_form(oracle_mod):
 
 
 def test_admission_properties(oracle_mod):
-    wl = workloads.cfg3(n_events=6, max_per_event=3)
+    wl = workloads.uneven_512_events(n_events=6, max_per_event=3)
     kappa = [2.0, 2.0, 20.0]
     solo = oracle_mod.Oracle(oracle_mod.DENSE, 0, 1 << 16, wl.seeds)
     assert solo.inject(wl.primaries) == 0
@@ -313,7 +313,7 @@ def test_admission_reservation_limits(oracle_mod):
     when no track is active; with hold 0 every admission satisfies
     n + sum of projected peaks <= alpha * C on the counts of that iteration.
     Per-event tallies never depend on the hold."""
-    wl = workloads.cfg3(n_events=12, max_per_event=2)
+    wl = workloads.uneven_512_events(n_events=12, max_per_event=2)
     kappa = [4.0, 4.0, 40.0]
     alpha, C = 0.5, 4096
     E = wl.event_energy()

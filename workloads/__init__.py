@@ -9,15 +9,15 @@ arrays produced here through the same binary record layout (``PRIMARY_DTYPE``,
 
 Workloads (energies in MeV, lengths in mm):
 
-* ``cfg0``: one event, 100 electrons of 1000 MeV at the origin along +z, seed 1.
-* ``cfg1``: one event, 10^4 electrons of 10^4 MeV, seed 1.
-* ``cfg2``: one event, 10^5 electrons of 10^4 MeV, seed 7.
-* ``cfg3``: 512 events of uneven size.  A ``numpy.random.Generator(PCG64(3))``
+* ``showers_100e_1gev``: one event, 100 electrons of 1000 MeV at the origin along +z, seed 1.
+* ``showers_10ke_10gev``: one event, 10^4 electrons of 10^4 MeV, seed 1.
+* ``showers_100ke_10gev``: one event, 10^5 electrons of 10^4 MeV, seed 7.
+* ``uneven_512_events``: 512 events of uneven size.  A ``numpy.random.Generator(PCG64(3))``
   draws the per-event primary counts ``integers(1, 2001, 512)``; then, event by
   event, ``random(N_e)`` picks the type (u < 0.7 electron, u < 0.9 photon, else
   positron) and a second ``random(N_e)`` the energy ``E = 100 * 1000**u``.
   Event ``e`` has seed ``e + 1``.
-* ``cfg4``: 1000 events x 1000 electrons of 10^4 MeV, event ``e`` seed ``e + 1``.
+* ``segmented_1000_events``: 1000 events x 1000 electrons of 10^4 MeV, event ``e`` seed ``e + 1``.
 
 Every primary starts at (0, 0, 0) moving along +z with its interaction length
 unset (``numIALeft = -1``: sampled at its first step), and its track id is its
@@ -81,22 +81,22 @@ class Workload:
                         self.seeds, self.description + f" (first {n_primaries} primaries)")
 
 
-def cfg0():
-    return Workload("cfg0", primaries(100, ELECTRON, 1000.0), [1],
+def showers_100e_1gev():
+    return Workload("showers_100e_1gev", primaries(100, ELECTRON, 1000.0), [1],
                     "1 event x 100 e- at 1 GeV, seed 1")
 
 
-def cfg1(n=10_000):
-    return Workload("cfg1", primaries(n, ELECTRON, 10_000.0), [1],
+def showers_10ke_10gev(n=10_000):
+    return Workload("showers_10ke_10gev", primaries(n, ELECTRON, 10_000.0), [1],
                     f"1 event x {n} e- at 10 GeV, seed 1")
 
 
-def cfg2(n=100_000):
-    return Workload("cfg2", primaries(n, ELECTRON, 10_000.0), [7],
+def showers_100ke_10gev(n=100_000):
+    return Workload("showers_100ke_10gev", primaries(n, ELECTRON, 10_000.0), [7],
                     f"1 event x {n} e- at 10 GeV, seed 7")
 
 
-def cfg3(n_events=512, max_per_event=2000):
+def uneven_512_events(n_events=512, max_per_event=2000):
     g = np.random.Generator(np.random.PCG64(3))
     counts = g.integers(1, max_per_event + 1, n_events)
     parts = []
@@ -109,16 +109,16 @@ def cfg3(n_events=512, max_per_event=2000):
         p["E"] = 100.0 * np.power(1000.0, ue)
         parts.append(p)
     prims = np.concatenate(parts)
-    return Workload("cfg3", prims, np.arange(1, n_events + 1),
+    return Workload("uneven_512_events", prims, np.arange(1, n_events + 1),
                     f"{n_events} events x U{{1..{max_per_event}}} primaries, 70/20/10 e-/gamma/e+, "
                     "E log-uniform in [100 MeV, 100 GeV], seeds e+1")
 
 
-def cfg4(n_events=1000, per_event=1000):
+def segmented_1000_events(n_events=1000, per_event=1000):
     parts = [primaries(per_event, ELECTRON, 10_000.0, event=e) for e in range(n_events)]
-    return Workload("cfg4", np.concatenate(parts), np.arange(1, n_events + 1),
+    return Workload("segmented_1000_events", np.concatenate(parts), np.arange(1, n_events + 1),
                     f"{n_events} events x {per_event} e- at 10 GeV, seeds e+1")
 
 
 def by_name(name, **kw):
-    return {"cfg0": cfg0, "cfg1": cfg1, "cfg2": cfg2, "cfg3": cfg3, "cfg4": cfg4}[name](**kw)
+    return {"showers_100e_1gev": showers_100e_1gev, "showers_10ke_10gev": showers_10ke_10gev, "showers_100ke_10gev": showers_100ke_10gev, "uneven_512_events": uneven_512_events, "segmented_1000_events": segmented_1000_events}[name](**kw)
