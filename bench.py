@@ -235,6 +235,7 @@ def batched_section(ad, torch, np, workloads, args):
     lay_m = sim.tally(ad.T_LAYER).reshape(len(wl.seeds), 50).sum(axis=0)
     sim.close()
     out["mixed"] = {"seconds": dt, "track_steps": ts, "track_steps_per_s": ts / dt, "iterations": it,
+                    "algorithmic_GBps_run": algorithmic_bytes(st, layout[0], 1) / dt / 1e9,
                     "primaries_per_s": len(wl.primaries) / dt, "divergent_wave_fraction": st["waves_divergent"] / max(st["waves"], 1)}
     # the FP64 sparse single buffer (the paper's baseline structure), same admission
     sp = ad.Sim(0, 0, ad.FP64, C, 1, seeds=wl.seeds, admission=(0.8, kappa), launch=launch)
@@ -242,7 +243,9 @@ def batched_section(ad, torch, np, workloads, args):
     lay_f = sp.tally(ad.T_LAYER).reshape(len(wl.seeds), 50).sum(axis=0)
     sp.close()
     ts2 = sum(st2["track_steps"])
-    out["fp64_sparse_aos"] = {"seconds": dt2, "track_steps_per_s": ts2 / dt2}
+    out["fp64_sparse_aos"] = {"seconds": dt2, "track_steps_per_s": ts2 / dt2,
+                              "algorithmic_GBps_run": algorithmic_bytes(st2, 0, 0) / dt2 / 1e9,
+                              "divergent_wave_fraction": st2["waves_divergent"] / max(st2["waves"], 1)}
     out["speedup_vs_fp64_sparse_aos"] = dt2 / dt
     rel = np.abs(lay_m - lay_f) / lay_f
     out["edep_per_layer_rel_error_mixed_vs_fp64"] = {"max": float(rel.max()),
@@ -434,10 +437,19 @@ def main():
         lm, lf = head["layer"], f64["layer"]
         rel = np.abs(lm - lf) / np.maximum(np.abs(lf), 1e-300)
         assert np.array_equal(lf, sp["layer"]) or np.allclose(lf, sp["layer"], rtol=1e-12)
+        def run_gbps(r, scheme, precision):  # algorithmic bytes of a run over its wall time
+            return algorithmic_bytes(r["stats"], scheme, precision) / (r["ms_per_step"] * 1e-3) / 1e9
+
+        def div(r):
+            return r["stats"]["waves_divergent"] / max(r["stats"]["waves"], 1)
+
         out["fp64_dense_soa"] = {"track_steps_per_s": f64["track_steps_per_s"], "ms_per_step": f64["ms_per_step"],
-                                 "closure_error": f64["closure"]}
+                                 "closure_error": f64["closure"], "algorithmic_GBps_run": run_gbps(f64, 1, 0),
+                                 "divergent_wave_fraction": div(f64)}
         out["fp64_sparse_aos"] = {"track_steps_per_s": sp["track_steps_per_s"], "ms_per_step": sp["ms_per_step"],
-                                  "closure_error": sp["closure"]}
+                                  "closure_error": sp["closure"], "algorithmic_GBps_run": run_gbps(sp, 0, 0),
+                                  "divergent_wave_fraction": div(sp)}
+        out["algorithmic_GBps_run"] = run_gbps(head, 1, 1)
         out["speedup_vs_fp64_sparse_aos"] = sp["ms_per_step"] / head["ms_per_step"]
         out["edep_per_layer_rel_error_mixed_vs_fp64"] = {
             "max": float(rel.max()), "max_over_layers_above_1e-3_of_total": float(rel[lf > 1e-3 * lf.sum()].max()),
