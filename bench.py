@@ -78,6 +78,9 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=9600, help="primaries of the workload run by the oracle")
     ap.add_argument("--headline-only", action="store_true", help="only the headline path (for profilers)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched uneven-events section")
+    ap.add_argument("--batched-profile", action="store_true",
+                    help="only the 512 uneven events, twice, with the tuned layout fixed (AoSoA-64, block 1024, "
+                         "graphs of 16): the command behind the batched kernel-trace summary")
     ap.add_argument("--per-event-sample", type=int, default=32, help="events timed one launch sequence each")
     ap.add_argument("--segmented", action="store_true", help="also run 10^6 e- in 1000 events with 500k cells")
     ap.add_argument("--layout-study", action="store_true",
@@ -264,6 +267,18 @@ def batched_section(ad, torch, np, workloads, args):
     return out
 
 
+def batched_profile(ad, torch, np, workloads):
+    wl = workloads.uneven_512_events()
+    sim = ad.Sim(ad.DENSE_DOUBLE, ad.MAP_AOSOA, ad.MIXED, 1 << 24, 64, seeds=wl.seeds,
+                 admission=(0.8, kappa_per_gev()), launch={"block": 1024, "graph_iters": 16})
+    runs = []
+    for _ in range(2):
+        dt, it, st = run_once(ad, torch, sim, wl.primaries)
+        runs.append({"seconds": dt, "iterations": it, "track_steps_per_s": sum(st["track_steps"]) / dt})
+    sim.close()
+    return {"workload": wl.description, "layout": "dense AoSoA-64, mixed", "runs": runs}
+
+
 def segmented_section(ad, torch, np, workloads):
     wl = workloads.segmented_1000_events()
     C = 1 << 28
@@ -383,6 +398,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.batched_profile:
+        print(json.dumps({"batched_profile": batched_profile(ad, torch, np, workloads)}), flush=True)
+        return
     wl = workloads.showers_100ke_10gev(args.primaries)
     C = 1 << args.capacity_log2
     dev_prims = torch.from_numpy(wl.primaries.view(np.uint8).copy()).cuda()
