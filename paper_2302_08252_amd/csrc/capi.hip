@@ -2,9 +2,11 @@
 // sequences (per-iteration launches and hipGraph replay), readback.
 //
 // Per iteration the stream sees
-//   [k_admit, k_inject, k_inject_epi]   (only with event admission)
+//   [k_inject, k_inject_epi]            (only with event admission)
 //   k_step                               (fixed grid, tile tickets, look-back)
-//   k_epilogue                           (one wavefront)
+//   k_epilogue                           (one wavefront; with admission it also
+//                                         admits the events of the next iteration)
+// and, with admission, one k_admit before the first iteration of a call.
 // and adept_run captures graph_iters such iterations into one hipGraph that it
 // replays until the host-mapped mirror reports that nothing is left.
 #include <hip/hip_runtime.h>
@@ -27,8 +29,7 @@ enum State { CREATED = 0, READY = 1, FAILED = 2 };
 // ---------------------------------------------------------------------------
 // Small kernels
 // ---------------------------------------------------------------------------
-__global__ void k_epilogue(const KArgs a) {
-  if (threadIdx.x != 0) return;
+__device__ void epilogue_body(const KArgs& a) {
   Ctrl* c = a.ctrl;
   HostMirror* m = a.mirror;
   if (c->error) return;
@@ -86,11 +87,11 @@ __global__ void k_epilogue(const KArgs a) {
 // `hold` iterations; groups are admitted in order while, for every type,
 // active + reserved + projected peak <= alpha * C (the first waiting group
 // always goes in when nothing is active).
-__global__ void k_admit(const KArgs a) {
-  if (threadIdx.x != 0) return;
+__device__ void admit_body(const KArgs& a) {
   Ctrl* c = a.ctrl;
   EventGroup* groups = const_cast<EventGroup*>(a.groups);
   c->inj_begin = c->inj_end = 0;
+  c->adm_for = c->iter + 1;
   if (c->error) return;
   const uint32_t p = c->parity;
   c->had_staged = c->next_group < c->n_groups ? 1u : 0u;
@@ -126,6 +127,21 @@ __global__ void k_admit(const KArgs a) {
     c->inj_end = groups[g - 1].first + groups[g - 1].count;
     c->next_group = g;
   }
+}
+
+// Admission before the first iteration a launch sequence runs, unless the last
+// iteration epilogue already decided it.
+__global__ void k_admit(const KArgs a) {
+  if (threadIdx.x != 0) return;
+  if (a.ctrl->adm_for != a.ctrl->iter + 1) admit_body(a);
+}
+
+// The iteration epilogue; with admission it also decides the next iteration's
+// (the same decision a separate launch before that iteration would take).
+__global__ void k_epilogue(const KArgs a) {
+  if (threadIdx.x != 0) return;
+  epilogue_body(a);
+  if (a.adm_on) admit_body(a);
 }
 
 __global__ void k_set_range(const KArgs a, unsigned long long begin, unsigned long long end) {
@@ -560,10 +576,7 @@ void launch_inject(adept_ctx* c, const KArgs& a, hipStream_t s) {
 void launch_iteration(adept_ctx* c, const KArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,
                       hipEvent_t e1 = nullptr) {
   const Ops& o = ops(c);
-  if (c->adm_on) {
-    hipLaunchKernelGGL(k_admit, dim3(1), dim3(64), 0, s, a);
-    launch_inject(c, a, s);
-  }
+  if (c->adm_on) launch_inject(c, a, s);  // admitted by k_admit or the previous epilogue
   if (e0) (void)hipEventRecord(e0, s);
   o.step(a, grid_of(c), c->launch.block, s);
   if (e1) (void)hipEventRecord(e1, s);
@@ -626,6 +639,10 @@ adept_status upload_staged(adept_ctx* c) {
   HIPCHK(hipMemcpyAsync(&dc->g_old, &zero, 8, hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(dc->reserved, none, sizeof(none), hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(&dc->n_groups, &ng, 8, hipMemcpyHostToDevice, c->stream));
+  // an admission decided against the old table is void: the next iteration decides again
+  HIPCHK(hipMemcpyAsync(&dc->adm_for, &zero, 8, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(&dc->inj_begin, &zero, 8, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(&dc->inj_end, &zero, 8, hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   c->staged_dirty = false;
   return ADEPT_OK;
@@ -915,6 +932,7 @@ adept_status adept_step(adept_ctx* c, uint64_t next_counts[3]) {
   if (rc) return rc;
   KArgs a = c->args;
   a.count_empty = 1;
+  if (c->adm_on) hipLaunchKernelGGL(k_admit, dim3(1), dim3(64), 0, c->stream, a);
   launch_iteration(c, a, c->stream);
   HIPCHK(hipGetLastError());
   rc = sync_mirror(c);
@@ -945,6 +963,8 @@ adept_status adept_run(adept_ctx* c, uint64_t max_iter, uint64_t* iters_done) {
     c->graph_valid = true;
     c->graph_k = K;
   }
+  if (c->adm_on) hipLaunchKernelGGL(k_admit, dim3(1), dim3(64), 0, c->stream, a);
+  HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->stream));
   const unsigned long long it0 = c->mirror->iter;
   c->mirror->done = 0;

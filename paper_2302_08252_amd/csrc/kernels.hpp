@@ -67,6 +67,7 @@ struct Ctrl {
   unsigned int parity, inj_parity;
   int error;
   unsigned int had_staged;
+  unsigned long long adm_for;       // admission: iterations done + 1 when the next one's admission is decided
   unsigned long long overflow;      // set by kernels that saw an index beyond capacity
 };
 
