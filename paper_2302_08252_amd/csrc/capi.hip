@@ -567,16 +567,20 @@ adept_status grow_staged(adept_ctx* c, unsigned long long n) {
   return ADEPT_OK;
 }
 
-void launch_inject(adept_ctx* c, const KArgs& a, hipStream_t s) {
+// Injection: every iteration of an admission run launches it, and most admit
+// nothing, so there a small grid (blocks loop over the tiles) keeps the idle
+// launch cheap; one explicit injection gets the full grid.
+constexpr unsigned kAdmitInjectGrid = 64;
+void launch_inject(adept_ctx* c, const KArgs& a, hipStream_t s, bool per_iteration) {
   const Ops& o = ops(c);
-  o.inject(a, grid_of(c), c->launch.block, s);
+  o.inject(a, per_iteration ? std::min(kAdmitInjectGrid, grid_of(c)) : grid_of(c), c->launch.block, s);
   hipLaunchKernelGGL(k_inject_epi, dim3(1), dim3(64), 0, s, a);
 }
 
 void launch_iteration(adept_ctx* c, const KArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,
                       hipEvent_t e1 = nullptr) {
   const Ops& o = ops(c);
-  if (c->adm_on) launch_inject(c, a, s);  // admitted by k_admit or the previous epilogue
+  if (c->adm_on) launch_inject(c, a, s, true);  // admitted by k_admit or the previous epilogue
   if (e0) (void)hipEventRecord(e0, s);
   o.step(a, grid_of(c), c->launch.block, s);
   if (e1) (void)hipEventRecord(e1, s);
@@ -659,7 +663,7 @@ bool valid_primary(const adept_ctx* c, const adept_primary& q) {
 // Inject n primaries already copied to c->staged[0..n).
 adept_status inject_staged(adept_ctx* c, unsigned long long n) {
   hipLaunchKernelGGL(k_set_range, dim3(1), dim3(64), 0, c->stream, c->args, 0ull, n);
-  launch_inject(c, c->args, c->stream);
+  launch_inject(c, c->args, c->stream, false);
   HIPCHK(hipGetLastError());
   c->graph_valid = c->graph_valid;  // the graph does not reference the range
   return sync_mirror(c);
