@@ -131,9 +131,13 @@ typedef struct {
   uint32_t pad;
 } adept_launch;
 
-/* Create a context.  capacity = slots per particle type and per buffer, in
- * [1, 2^30]; for AoSoA a multiple of aosoa_lanes.  The layout, precision and
- * capacity are fixed for the context's lifetime.  Errors: ADEPT_E_INVALID. */
+/* Create a context (paper Sec. 2: the track data structure, one of its two
+ * buffer schemes; Sec. 3-4: the record layout its buffers use).  capacity =
+ * slots per particle type and per buffer, in [1, 2^30]; for AoSoA a multiple
+ * of aosoa_lanes.  The layout, precision and capacity are fixed for the
+ * context's lifetime.  The context owns its host state; device memory comes at
+ * the first call that needs it (or from adept_bind).  Errors: ADEPT_E_INVALID
+ * (nothing is created, *out untouched), ADEPT_E_DEVICE. */
 adept_status adept_create(adept_layout layout, adept_precision precision, uint64_t capacity, adept_ctx** out);
 
 /* Create a context whose particle types keep their tracks in different record
@@ -187,7 +191,9 @@ adept_status adept_set_instrumented(adept_ctx* ctx, int on, uint64_t last_iter);
 adept_status adept_set_launch(adept_ctx* ctx, const adept_launch* launch);
 adept_status adept_get_launch(const adept_ctx* ctx, adept_launch* launch);
 
-/* Primaries (copied).  Without admission they pass through the creation path
+/* Primaries (copied; paper Sec. 2: new tracks enter the list of active tracks
+ * of their particle type, Sec. 4: the benchmark feeds primaries in batches).
+ * Without admission they pass through the creation path
  * at once, in input order, appended after the current tracks of their type;
  * with admission they must be grouped by non-decreasing event and wait to be
  * admitted (staging is only allowed before the first iteration).  Errors: ADEPT_E_INVALID (bad primary; nothing is injected),
@@ -200,21 +206,38 @@ adept_status adept_inject(adept_ctx* ctx, const adept_primary* p, uint64_t n);
  * available with admission (ADEPT_E_UNSUPPORTED). */
 adept_status adept_inject_device(adept_ctx* ctx, const adept_primary* dev_p, uint64_t n);
 
-/* Exactly one iteration (admission, then one step of every active track);
- * synchronous; next_counts (nullable) receives the active counts per type. */
+/* Exactly one iteration (paper Sec. 2: every active track of the current
+ * buffer is stepped once and survivors plus secondaries are written to the
+ * next buffer / slot list): admission, then one step of every active track;
+ * synchronous; next_counts (nullable, 3 host words owned by the caller)
+ * receives the active counts per type.  Errors: ADEPT_E_CAPACITY (a next
+ * buffer or the free ring overflowed: the context is failed),
+ * ADEPT_E_DEVICE, ADEPT_E_STATE. */
 adept_status adept_step(adept_ctx* ctx, uint64_t next_counts[3]);
 
-/* Iterate until no track is active and nothing is staged, or max_iter
- * iterations; iterations replay a captured hipGraph of graph_iters iterations.
- * iters_done (nullable) receives the iterations done by this call. */
+/* Iterate (paper Sec. 2 iterations, Sec. 4: a benchmark run transports every
+ * primary to the end of its shower) until no track is active and nothing is
+ * staged, or max_iter iterations; iterations replay a captured hipGraph of
+ * graph_iters iterations.  iters_done (nullable, caller-owned) receives the
+ * iterations done by this call.  Errors as adept_step; on an error the
+ * iterations before it stay done. */
 adept_status adept_run(adept_ctx* ctx, uint64_t max_iter, uint64_t* iters_done);
 
-/* Copy a tally out; n must equal the kind's size (see adept_tally_kind). */
+/* Copy a tally out (paper Sec. 4: the energy deposited in the layers of the
+ * sampling calorimeter; the per-event, per-volume and per-cell forms here):
+ * out is a caller-owned host array of n doubles; n must equal the kind's size
+ * (see adept_tally_kind), else ADEPT_E_INVALID and out is untouched.  Valid on
+ * a failed context too (the state at the failure). */
 adept_status adept_tally(adept_ctx* ctx, adept_tally_kind kind, double* out, size_t n);
 
-/* Access counts of one physical buffer (buffer 0, or 1 = second dense array):
- * reads/writes per field (14 each, nullable) and, if heat_words is not NULL,
- * the per-4-byte-word access counters (n_words must equal the buffer size / 4). */
+/* Access counts of one physical buffer (paper Sec. 5: field access counts of
+ * the Trace instrumentation and the per-byte Heatmap; buffer 0, or 1 = second
+ * dense array): reads/writes per field (14 host words each, nullable) and, if
+ * heat_words is not NULL, the per-4-byte-word access counters (a caller-owned
+ * host array; n_words must equal the buffer size / 4; every field is a
+ * multiple of 4 bytes and 4-aligned, so a word's count is each of its bytes'
+ * count).  Zero unless the context is instrumented.  Errors: ADEPT_E_INVALID,
+ * ADEPT_E_STATE (no device state yet). */
 adept_status adept_access_counts(adept_ctx* ctx, adept_particle t, uint32_t buffer, uint64_t reads[14],
                                  uint64_t writes[14], uint32_t* heat_words, size_t n_words);
 

@@ -23,6 +23,24 @@ def test_header_declares_the_core_entry_points():
         assert core in names
 
 
+def _comment_before(text, name):
+    """The comment block right before the declaration of entry point `name`."""
+    m = re.search(r"(/\*(?:(?!\*/).)*\*/)\s*adept_status\s+" + name + r"\s*\(", text, flags=re.S)
+    return m.group(1) if m else ""
+
+
+def test_core_declarations_cite_the_defining_passage():
+    """Each of the six core calls says which section of the paper defines the
+    operation it performs (and its error behaviour)."""
+    text = open(HEADER).read()
+    for core, sec in (("adept_create", "Sec. 2"), ("adept_inject", "Sec. 2"), ("adept_step", "Sec. 2"),
+                      ("adept_run", "Sec. 2"), ("adept_tally", "Sec. 4"), ("adept_access_counts", "Sec. 5")):
+        c = _comment_before(text, core)
+        assert c, core
+        assert sec in c, (core, c)
+        assert "Errors" in c or "ADEPT_E_" in c, core
+
+
 def test_library_exports_every_declared_symbol():
     import paper_2302_08252_amd as ad
 
