@@ -55,15 +55,34 @@ class Stats(ctypes.Structure):
     ]
 
 
-def build(force=False):
-    """Compile liboracle.so with gcc (no FMA contraction, no fast-math)."""
-    if not force and os.path.exists(LIB):
-        if os.path.getmtime(LIB) >= max(os.path.getmtime(SRC), os.path.getmtime(HDR)):
-            return LIB
-    tmp = LIB + ".tmp"
-    subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, SRC, "-lm"])
-    os.replace(tmp, LIB)
-    return LIB
+class Ledger(ctypes.Structure):
+    _fields_ = [
+        ("primaries", ctypes.c_uint64 * 3),
+        ("created", ctypes.c_uint64 * 3),
+        ("escaped", ctypes.c_uint64 * 3),
+        ("cut", ctypes.c_uint64 * 3),
+        ("annihilated", ctypes.c_uint64),
+        ("absorbed", ctypes.c_uint64),
+        ("n_brem", ctypes.c_uint64),
+        ("n_pair", ctypes.c_uint64),
+        ("n_compton", ctypes.c_uint64),
+        ("n_annihilation", ctypes.c_uint64),
+        ("survivors", ctypes.c_uint64 * 3),
+        ("outputs", ctypes.c_uint64 * 3),
+    ]
+
+
+def build(force=False, src=SRC, out=LIB, extra_flags=()):
+    """Compile liboracle.so with gcc (no FMA contraction, no fast-math).  src/out
+    build another copy of the source (the mutation tests compile altered copies;
+    extra_flags adds e.g. sanitizer options)."""
+    if not force and os.path.exists(out):
+        if os.path.getmtime(out) >= max(os.path.getmtime(src), os.path.getmtime(HDR)):
+            return out
+    tmp = out + ".tmp"
+    subprocess.check_call(["gcc", *CFLAGS, *extra_flags, "-I", HERE, "-o", tmp, src, "-lm"])
+    os.replace(tmp, out)
+    return out
 
 
 _lib = None
@@ -73,53 +92,59 @@ def lib():
     global _lib
     if _lib is None:
         build()
-        L = ctypes.CDLL(LIB)
-        P = ctypes.c_void_p
-        u64, u32, i32, dbl, flt = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_double, ctypes.c_float
-        sig = {
-            "or_create": (P, [i32, i32, u64, u32, P]),
-            "or_destroy": (None, [P]),
-            "or_set_scoring": (i32, [P, u32, u32, dbl]),
-            "or_set_instrumented": (i32, [P, i32, u64]),
-            "or_set_admission": (i32, [P, i32, dbl, P, u64]),
-            "or_inject": (i32, [P, P, u64]),
-            "or_stage": (i32, [P, P, u64]),
-            "or_step": (i32, [P, P]),
-            "or_run": (i32, [P, u64, P]),
-            "or_counts": (i32, [P, P]),
-            "or_tally": (i32, [P, i32, P, ctypes.c_size_t]),
-            "or_stats_get": (i32, [P, P]),
-            "or_dump": (i32, [P, i32, P, P, u64, P]),
-            "or_load": (i32, [P, i32, P, P, u64]),
-            "or_ring_get": (i32, [P, i32, P, P, P]),
-            "or_ring_set": (i32, [P, i32, P, u64, u64]),
-            "or_set_iteration": (i32, [P, u64, i32]),
-            "or_access_totals": (i32, [P, i32, i32, P, P]),
-            "or_access_slotleaf": (i32, [P, i32, i32, P, u64]),
-            "or_heat_words": (i32, [P, i32, i32, i32, u32, P, u64]),
-            "or_philox4x32_10": (None, [P, P, P]),
-            "or_u01": (dbl, [u32]),
-            "or_u01f": (flt, [u32]),
-            "or_log": (dbl, [dbl]),
-            "or_exp": (dbl, [dbl]),
-            "or_sincos": (None, [dbl, P, P]),
-            "or_logf": (flt, [flt]),
-            "or_expf": (flt, [flt]),
-            "or_sincosf": (None, [flt, P, P]),
-            "or_constants": (None, [P, P]),
-            "or_leaf_addr": (u64, [i32, u32, i32, u64, u64, i32]),
-            "or_buffer_bytes": (u64, [i32, u32, i32, u64]),
-            "or_leaf_size": (u32, [i32, i32]),
-            "or_child_id": (u64, [u32, u64, u32, u32]),
-            "or_locate": (i32, [P, P]),
-            "or_distance": (dbl, [P, P, i32, P]),
-        }
-        for name, (res, args) in sig.items():
-            f = getattr(L, name)
-            f.restype = res
-            f.argtypes = args
-        _lib = L
+        _lib = load(LIB)
     return _lib
+
+
+def load(path):
+    """A ctypes handle of an oracle library built from (a copy of) oracle.c."""
+    L = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    u64, u32, i32, dbl, flt = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_double, ctypes.c_float
+    sig = {
+        "or_create": (P, [i32, i32, u64, u32, P]),
+        "or_destroy": (None, [P]),
+        "or_set_scoring": (i32, [P, u32, u32, dbl]),
+        "or_set_instrumented": (i32, [P, i32, u64]),
+        "or_set_admission": (i32, [P, i32, dbl, P, u64]),
+        "or_inject": (i32, [P, P, u64]),
+        "or_stage": (i32, [P, P, u64]),
+        "or_step": (i32, [P, P]),
+        "or_run": (i32, [P, u64, P]),
+        "or_counts": (i32, [P, P]),
+        "or_tally": (i32, [P, i32, P, ctypes.c_size_t]),
+        "or_stats_get": (i32, [P, P]),
+        "or_ledger_get": (i32, [P, P]),
+        "or_dump": (i32, [P, i32, P, P, u64, P]),
+        "or_load": (i32, [P, i32, P, P, u64]),
+        "or_ring_get": (i32, [P, i32, P, P, P]),
+        "or_ring_set": (i32, [P, i32, P, u64, u64]),
+        "or_set_iteration": (i32, [P, u64, i32]),
+        "or_access_totals": (i32, [P, i32, i32, P, P]),
+        "or_access_slotleaf": (i32, [P, i32, i32, P, u64]),
+        "or_heat_words": (i32, [P, i32, i32, i32, u32, P, u64]),
+        "or_philox4x32_10": (None, [P, P, P]),
+        "or_u01": (dbl, [u32]),
+        "or_u01f": (flt, [u32]),
+        "or_log": (dbl, [dbl]),
+        "or_exp": (dbl, [dbl]),
+        "or_sincos": (None, [dbl, P, P]),
+        "or_logf": (flt, [flt]),
+        "or_expf": (flt, [flt]),
+        "or_sincosf": (None, [flt, P, P]),
+        "or_constants": (None, [P, P]),
+        "or_leaf_addr": (u64, [i32, u32, i32, u64, u64, i32]),
+        "or_buffer_bytes": (u64, [i32, u32, i32, u64]),
+        "or_leaf_size": (u32, [i32, i32]),
+        "or_child_id": (u64, [u32, u64, u32, u32]),
+        "or_locate": (i32, [P, P]),
+        "or_distance": (dbl, [P, P, i32, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
 
 
 def _ptr(a):
@@ -135,8 +160,8 @@ class OracleError(RuntimeError):
 class Oracle:
     """One simulation context of the oracle."""
 
-    def __init__(self, scheme=DENSE, precision=FP64, capacity=1 << 20, seeds=(1,)):
-        self.L = lib()
+    def __init__(self, scheme=DENSE, precision=FP64, capacity=1 << 20, seeds=(1,), L=None):
+        self.L = L if L is not None else lib()
         seeds = np.ascontiguousarray(seeds, dtype=np.uint32)
         self.h = self.L.or_create(scheme, precision, int(capacity), len(seeds), _ptr(seeds))
         if not self.h:
@@ -206,6 +231,15 @@ class Oracle:
         self.L.or_stats_get(self.h, ctypes.byref(s))
         return {"iterations": s.iterations, "track_steps": list(s.track_steps), "peak": list(s.peak),
                 "slots_touched": list(s.slots_touched), "error_iter": s.error_iter, "status": s.status}
+
+    def ledger(self):
+        """The particle ledger (see oracle.h) plus the active counts ("inflight")."""
+        g = Ledger()
+        self._check(self.L.or_ledger_get(self.h, ctypes.byref(g)), "ledger")
+        out = {name: (list(getattr(g, name)) if isinstance(getattr(g, name), ctypes.Array) else getattr(g, name))
+               for name, _ in Ledger._fields_}
+        out["inflight"] = [int(x) for x in self.counts()]
+        return out
 
     def dump(self, ptype):
         n = int(self.counts()[ptype])

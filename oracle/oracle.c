@@ -410,6 +410,7 @@ struct or_sim {
   uint64_t n_groups, next_group;
   /* stats */
   uint64_t iter, steps[3], peak[3], slots_hw[3], error_iter;
+  or_ledger led;
   int status;
   /* scratch outputs of one iteration */
   outrec *out;
@@ -582,11 +583,15 @@ static void create(or_sim *S, creator *X, int type, double E, const double pos[3
   int subcut;
   if (S->prec == OR_MIXED) subcut = (type == OR_GAMMA) ? ((float)E < kCUTGf) : ((float)E < kCUTEf);
   else subcut = (type == OR_GAMMA) ? (E < kCUTG) : (E < kCUTE);
+  S->led.created[type] += 1;
   if (subcut) {
     tally_cut(S, X->event, v, E, pos);
     if (type == OR_POSITRON) {
+      S->led.annihilated += 1;
       creator V = {X->seed, X->event, id, 0u, 0};
       annihilate(S, &V, pos, v, out);
+    } else {
+      S->led.cut[type] += 1;
     }
     return;
   }
@@ -610,6 +615,7 @@ static void create(or_sim *S, creator *X, int type, double E, const double pos[3
 /* Annihilation at rest of X at its step n: cos(theta) = 2U(b1) - 1, phi = 2 pi U(b2),
  * d = (sin theta cos phi, sin theta sin phi, cos theta); photons of m_e along +d, then -d. */
 static void annihilate(or_sim *S, creator *X, const double pos[3], int v, creations *out) {
+  S->led.n_annihilation += 1;
   uint32_t b[4];
   track_block(X->seed, X->id, X->n, 1u, b);
   double d[3], md[3], Eg;
@@ -680,6 +686,17 @@ static int advance(double pos[3], double p0[3], const double dir[3], double s, i
   return lim == LIM_GEOM ? cross(pos, dir, v, axis) : v;
 }
 
+/* An electron below the cut stops (its energy is already booked); a positron
+ * annihilates at rest into two photons. */
+static void charged_death(or_sim *S, int type, creator *X, const double pos[3], int v1, creations *out) {
+  if (type == OR_POSITRON) {
+    S->led.annihilated += 1;
+    annihilate(S, X, pos, v1, out);
+  } else {
+    S->led.cut[type] += 1;
+  }
+}
+
 /* ---- e+- step, binary64 policy.  Returns 1 if the track survives. */
 static int step_charged_d(or_sim *S, int type, or_track *t, creations *out) {
   const uint32_t n = t->rngCtr;
@@ -713,11 +730,12 @@ static int step_charged_d(or_sim *S, int type, or_track *t, creations *out) {
   if (v1 == OUTSIDE) {
     nadd(&S->escaped[ev], E1);
     if (type == OR_POSITRON) nadd(&S->escaped[ev], rest2(S));
+    S->led.escaped[type] += 1;
     return 0;
   }
   if (E1 < kCUTE) {
     tally_cut(S, ev, v, E1, t->pos);
-    if (type == OR_POSITRON) annihilate(S, &X, t->pos, v1, out);
+    charged_death(S, type, &X, t->pos, v1, out);
     return 0;
   }
   /* multiple scattering with the pre-step energy */
@@ -734,12 +752,13 @@ static int step_charged_d(or_sim *S, int type, or_track *t, creations *out) {
     k = dmin(dmax(k, kKMIN), E1);
     const double E2 = E1 - k;
     k = E1 - E2;
+    S->led.n_brem += 1;
     create(S, &X, OR_GAMMA, k, t->pos, t->dir, v1, out);
     nl = -or_log(or_u01(b[0]));
     E = E2;
     if (E2 < kCUTE) {
       tally_cut(S, ev, v, E2, t->pos);
-      if (type == OR_POSITRON) annihilate(S, &X, t->pos, v1, out);
+      charged_death(S, type, &X, t->pos, v1, out);
       return 0;
     }
   }
@@ -787,11 +806,12 @@ static int step_charged_m(or_sim *S, int type, or_track *t, creations *out) {
   if (v1 == OUTSIDE) {
     nadd(&S->escaped[ev], (double)E1);
     if (type == OR_POSITRON) nadd(&S->escaped[ev], rest2(S));
+    S->led.escaped[type] += 1;
     return 0;
   }
   if (E1 < kCUTEf) {
     tally_cut(S, ev, v, (double)E1, t->pos);
-    if (type == OR_POSITRON) annihilate(S, &X, t->pos, v1, out);
+    charged_death(S, type, &X, t->pos, v1, out);
     return 0;
   }
   const float th0 = (kMSCf / E0) * sqrtf(sf / lam);
@@ -809,12 +829,13 @@ static int step_charged_m(or_sim *S, int type, or_track *t, creations *out) {
     k = fminn(fmaxx(k, kKMINf), E1);
     const float E2 = E1 - k;
     k = E1 - E2;
+    S->led.n_brem += 1;
     create(S, &X, OR_GAMMA, (double)k, t->pos, t->dir, v1, out);
     nl = -or_logf(or_u01f(b[0]));
     E = E2;
     if (E2 < kCUTEf) {
       tally_cut(S, ev, v, (double)E2, t->pos);
-      if (type == OR_POSITRON) annihilate(S, &X, t->pos, v1, out);
+      charged_death(S, type, &X, t->pos, v1, out);
       return 0;
     }
   }
@@ -849,9 +870,12 @@ static int step_photon_d(or_sim *S, or_track *t, creations *out) {
   nl = (lim == LIM_PHYS) ? 0.0 : dmax(nl - s / lam, 0.0);
   if (v1 == OUTSIDE) {
     nadd(&S->escaped[ev], E);
+    S->led.escaped[OR_GAMMA] += 1;
     return 0;
   }
   if (lim == LIM_PHYS && pair) {
+    S->led.n_pair += 1;
+    S->led.absorbed += 1;
     double T, r;
     two_sum(E, -kPAIRTH, &T, &r);
     nadd(&S->round[ev], r);
@@ -864,6 +888,7 @@ static int step_photon_d(or_sim *S, or_track *t, creations *out) {
   }
   double Enew = E;
   if (lim == LIM_PHYS) {
+    S->led.n_compton += 1;
     double T = or_u01(a[3]) * E;
     const double Ep = E - T;
     T = E - Ep;
@@ -872,6 +897,7 @@ static int step_photon_d(or_sim *S, or_track *t, creations *out) {
     Enew = Ep;
     if (Ep < kCUTG) {
       tally_cut(S, ev, v, Ep, t->pos);
+      S->led.cut[OR_GAMMA] += 1;
       return 0;
     }
   }
@@ -906,9 +932,12 @@ static int step_photon_m(or_sim *S, or_track *t, creations *out) {
   nl = (lim == LIM_PHYS) ? 0.0f : fmaxx(nl - (float)s / lam, 0.0f);
   if (v1 == OUTSIDE) {
     nadd(&S->escaped[ev], (double)E);
+    S->led.escaped[OR_GAMMA] += 1;
     return 0;
   }
   if (lim == LIM_PHYS && pair) {
+    S->led.n_pair += 1;
+    S->led.absorbed += 1;
     float T, r;
     two_sumf(E, -kPAIRTHf, &T, &r);
     nadd(&S->round[ev], (double)r);
@@ -921,6 +950,7 @@ static int step_photon_m(or_sim *S, or_track *t, creations *out) {
   }
   float Enew = E;
   if (lim == LIM_PHYS) {
+    S->led.n_compton += 1;
     float T = or_u01f(a[3]) * E;
     const float Ep = E - T;
     T = E - Ep;
@@ -929,6 +959,7 @@ static int step_photon_m(or_sim *S, or_track *t, creations *out) {
     Enew = Ep;
     if (Ep < kCUTGf) {
       tally_cut(S, ev, v, (double)Ep, t->pos);
+      S->led.cut[OR_GAMMA] += 1;
       return 0;
     }
   }
@@ -1083,11 +1114,15 @@ static int inject_range(or_sim *S, const or_primary *p, uint64_t n) {
     int subcut;
     if (S->prec == OR_MIXED) subcut = (q->type == OR_GAMMA) ? ((float)t.E < kCUTGf) : ((float)t.E < kCUTEf);
     else subcut = (q->type == OR_GAMMA) ? (t.E < kCUTG) : (t.E < kCUTE);
+    S->led.primaries[q->type] += 1;
     if (subcut) {
       tally_cut(S, ev, v, t.E, t.pos);
       if (q->type == OR_POSITRON) {
+        S->led.annihilated += 1;
         creator X = {t.rngSeed, ev, t.trackId, 0u, 0};
         annihilate(S, &X, t.pos, v, &cr);
+      } else {
+        S->led.cut[q->type] += 1;
       }
       for (int k = 0; k < cr.n; ++k)
         if (push_out(S, &cr.trk[k], cr.type[k], 0, 0) != OR_OK) return OR_E_NOMEM;
@@ -1207,6 +1242,7 @@ int or_step(or_sim *S, uint64_t next_counts[3]) {
       const int surv = step_track(S, D, &trk, &cr);
       S->steps[D] += 1;
       if (surv) {
+        S->led.survivors[D] += 1;
         if (count_on && S->scheme == OR_DENSE) count_leaf(S, D, b, slot, 9, 0);
         if (push_out(S, &trk, D, 1, slot) != OR_OK) return OR_E_NOMEM;
       } else if (S->scheme == OR_SPARSE) {
@@ -1225,6 +1261,7 @@ int or_step(or_sim *S, uint64_t next_counts[3]) {
   for (int t = 0; t < 3; ++t) {
     if (S->scheme == OR_DENSE ? (nn[t] > S->C) : (alloc[t] > S->count[t])) return fail_capacity(S, t_iter);
   }
+  for (int t = 0; t < 3; ++t) S->led.outputs[t] += nn[t];
   if (S->scheme == OR_DENSE) {
     for (int t = 0; t < 3; ++t)
       if (dense_reserve(S, t, 1 - S->cur[t], nn[t]) != OR_OK) return OR_E_NOMEM;
@@ -1366,6 +1403,11 @@ int or_stats_get(const or_sim *S, or_stats *o) {
   return OR_OK;
 }
 
+int or_ledger_get(const or_sim *S, or_ledger *o) {
+  *o = S->led;
+  return OR_OK;
+}
+
 int or_dump(const or_sim *S, int type, or_track *out, uint32_t *slots, uint64_t cap, uint64_t *n) {
   if (type < 0 || type > 2) return OR_E_INVALID;
   *n = S->n[type];
@@ -1412,10 +1454,23 @@ int or_ring_set(or_sim *S, int type, const uint32_t *ring, uint64_t head, uint64
   return OR_OK;
 }
 
+/* Hand-over of a state: the iteration count, and (dense) which physical buffer,
+ * A or B, holds the current tracks.  Tracks already loaded stay current: they
+ * move with the label (the two buffers swap). */
 int or_set_iteration(or_sim *S, uint64_t iter, int dense_current_b) {
   S->iter = iter;
   if (S->scheme == OR_DENSE)
-    for (int t = 0; t < 3; ++t) S->cur[t] = dense_current_b ? 1 : 0;
+    for (int t = 0; t < 3; ++t) {
+      const int want = dense_current_b ? 1 : 0;
+      if (S->cur[t] == want) continue;
+      or_track *bp = S->buf[t][0];
+      uint64_t cap = S->bufcap[t][0];
+      S->buf[t][0] = S->buf[t][1];
+      S->bufcap[t][0] = S->bufcap[t][1];
+      S->buf[t][1] = bp;
+      S->bufcap[t][1] = cap;
+      S->cur[t] = want;
+    }
   return OR_OK;
 }
 

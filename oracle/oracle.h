@@ -73,6 +73,25 @@ typedef struct {
   int32_t pad;
 } or_stats;
 
+/* Particle ledger (integers, exact), kept for the invariant pins: every track
+ * that enters a type's list (primary or creation, sub-cut ones included) ends
+ * in exactly one of escaped / cut / annihilated (positrons) / absorbed by pair
+ * production (photons), or is still in flight.  Interactions are counted where
+ * each process branch is taken, creations where the creation path runs, deaths
+ * where the track dies, so the relations between them check that each process
+ * makes the particles it should. */
+typedef struct {
+  uint64_t primaries[3];  /* injected primaries per type                              */
+  uint64_t created[3];    /* tracks made by the creation path per type                */
+  uint64_t escaped[3];    /* left the calorimeter                                     */
+  uint64_t cut[3];        /* stopped below the cut (electrons, photons)               */
+  uint64_t annihilated;   /* positrons that annihilated at rest                       */
+  uint64_t absorbed;      /* photons absorbed by pair production                      */
+  uint64_t n_brem, n_pair, n_compton, n_annihilation;  /* interactions                */
+  uint64_t survivors[3];  /* source tracks that survived their step (all iterations)  */
+  uint64_t outputs[3];    /* tracks written into the next buffers (all iterations)    */
+} or_ledger;
+
 typedef struct or_sim or_sim;
 
 or_sim *or_create(int scheme, int precision, uint64_t capacity, uint32_t n_events, const uint32_t *seeds);
@@ -87,6 +106,7 @@ int or_run(or_sim *s, uint64_t max_iter, uint64_t *iters_done);
 int or_counts(const or_sim *s, uint64_t n[3]);
 int or_tally(const or_sim *s, int kind, double *out, size_t n);
 int or_stats_get(const or_sim *s, or_stats *out);
+int or_ledger_get(const or_sim *s, or_ledger *out);
 int or_dump(const or_sim *s, int type, or_track *out, uint32_t *slots, uint64_t cap, uint64_t *n);
 int or_load(or_sim *s, int type, const or_track *trk, const uint32_t *slots, uint64_t n);
 int or_ring_get(const or_sim *s, int type, uint32_t *ring, uint64_t *head, uint64_t *count);
