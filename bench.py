@@ -82,9 +82,11 @@ def parse():
                     help="only the 512 uneven events, twice, with the tuned layout fixed (AoSoA-64, block 1024, "
                          "graphs of 16): the command behind the batched kernel-trace summary")
     ap.add_argument("--per-event-sample", type=int, default=32, help="events timed one launch sequence each")
-    ap.add_argument("--segmented", action="store_true", help="also run 10^6 e- in 1000 events with 500k cells")
-    ap.add_argument("--layout-study", action="store_true",
-                    help="also time showers_10ke_10gev in the paper's four layouts and summarise its access counts")
+    ap.add_argument("--no-segmented", action="store_true", help="skip 10^6 e- in 1000 events with 500k cells")
+    ap.add_argument("--no-layout-study", action="store_true",
+                    help="skip showers_10ke_10gev in the paper's four layouts (timings and access counts)")
+    ap.add_argument("--flip-sample", type=int, default=512,
+                    help="primaries whose showers the oracle runs in both precision policies (flip count)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device to device (a plain copy of known size for scaling counters)")
     return ap.parse_args()
@@ -107,6 +109,17 @@ def algorithmic_bytes(st, scheme, precision):
     created = outs - surv
     killed = src - surv
     return src * (R + 4) + surv_w + outs * 4 + created * (W + 4) + killed * 4
+
+
+def kernel_roofline(st, scheme, precision):
+    """Step-kernel roofline of one timed run: its algorithmic bytes over the summed
+    HIP-event durations of its step-kernel launches."""
+    alg = algorithmic_bytes(st, scheme, precision)
+    ks = st["step_kernel_ms"] / 1e3
+    gbps = alg / ks / 1e9 if ks > 0 else None
+    return {"bound": "hbm", "kernel": "k_step", "achieved": gbps, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": gbps / PEAK_HBM_GBS if gbps else None, "algorithmic_bytes": alg,
+            "step_launches": st["step_launches"], "avg_step_kernel_ms": st["step_kernel_ms"] / max(st["step_launches"], 1)}
 
 
 def time_path(ad, torch, wl, dev_prims, scheme, mapping, precision, C, args, steps, warmup, timing):
@@ -157,31 +170,64 @@ def time_path(ad, torch, wl, dev_prims, scheme, mapping, precision, C, args, ste
     }
 
 
-def cpu_baseline(wl, sample, precision):
+# Worker processes of the CPU baseline: the host cores this process may use, capped at
+# 16, the CPU share that goes with one GPU on the benchmark boxes (their affinity
+# mask may show more cores than that share).
+CPU_SHARE = 16
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, sample, precision, repeats=3, flip_sample=64):
     """The oracle, unchanged, on a bounded sample of the workload: disjoint chunks of
-    primaries in worker processes (track histories do not depend on batching)."""
+    primaries in worker processes (track histories do not depend on batching), best of
+    `repeats` timed runs, plus a one-core rate.  Runs before the process touches the
+    GPU, so the forked workers inherit no HIP runtime state.  Also (untimed) the
+    mixed-precision flip count on `flip_sample` primaries: each primary's shower run by
+    the oracle under both precision policies, a shower counted as flipped when its
+    discrete history (per-type steps, creations, deaths and interactions) differs."""
     import multiprocessing as mp
 
     import oracle
 
     oracle.build()
-    cores = max(1, min(16, os.cpu_count() or 1))
+    avail = len(os.sched_getaffinity(0))
+    cores = max(1, min(CPU_SHARE, avail))
     prims = wl.primaries[:sample]
     chunks = [prims[i::cores] for i in range(cores)]
     args = [(c, wl.seeds, precision) for c in chunks if len(c)]
-    t0 = time.perf_counter()
+    times = []
     with mp.get_context("fork").Pool(len(args)) as pool:
-        steps = pool.map(_oracle_chunk, args)
-    dt = time.perf_counter() - t0
+        for _ in range(repeats):
+            t0 = time.perf_counter()
+            steps = pool.map(_oracle_chunk, args)
+            times.append(time.perf_counter() - t0)
+        flips = pool.map(_oracle_flip, [(p, wl.seeds) for p in wl.primaries[:flip_sample]])
+    dt = min(times)
     # one core on a twentieth of the sample, for the per-core rate
     t1 = time.perf_counter()
     steps1 = _oracle_chunk((prims[:max(1, sample // 20)], wl.seeds, precision))
     dt1 = time.perf_counter() - t1
     return {"value": sum(steps) / dt, "unit": "track-steps/s", "cores": len(args), "kind": "oracle",
+            "cpu_model": cpu_model(), "cores_available": avail,
+            "cores_note": f"worker processes = min(affinity {avail}, {CPU_SHARE}): {CPU_SHARE} host cores is the "
+                          "CPU share of one GPU on the benchmark boxes",
             "sample": f"first {sample} primaries of the workload, dense double buffer, "
-                      f"{'mixed' if precision else 'FP64'} policy, {sum(steps)} track-steps in {dt:.2f} s wall",
+                      f"{'mixed' if precision else 'FP64'} policy, {sum(steps)} track-steps, best of {repeats} "
+                      f"runs: {dt:.2f} s wall (runs {', '.join(f'{t:.2f}' for t in times)} s)",
             "single_core": {"value": steps1 / dt1, "sample": f"first {max(1, sample // 20)} primaries, "
-                                                              f"{steps1} track-steps in {dt1:.2f} s"}}
+                                                              f"{steps1} track-steps in {dt1:.2f} s"},
+            "mixed_precision_flips": {"primaries_compared": len(flips), "showers_with_a_flip": int(sum(flips)),
+                                      "method": "each primary's shower run alone by the oracle in FP64 and mixed; "
+                                                "flipped if any discrete count differs"}}
 
 
 def _oracle_chunk(a):
@@ -193,6 +239,25 @@ def _oracle_chunk(a):
     o, rc, _ = oracle.run_workload(wl, oracle.DENSE, precision, 1 << 24)
     assert rc == 0
     return sum(o.stats()["track_steps"])
+
+
+def _oracle_flip(a):
+    """1 if one primary's shower differs in any discrete count between the policies."""
+    import numpy as np
+
+    import oracle
+    import workloads
+
+    prim, seeds = a
+    hist = []
+    for precision in (oracle.FP64, oracle.MIXED):
+        wl = workloads.Workload("one", np.array([prim]), seeds, "")
+        o, rc, it = oracle.run_workload(wl, oracle.DENSE, precision, 1 << 22)
+        assert rc == 0
+        g = o.ledger()
+        hist.append((it, tuple(o.stats()["track_steps"]), tuple(g["created"]), tuple(g["escaped"]),
+                     tuple(g["cut"]), g["n_brem"], g["n_pair"], g["n_compton"], g["n_annihilation"]))
+    return int(hist[0] != hist[1])
 
 
 def kappa_per_gev():
@@ -236,10 +301,18 @@ def batched_section(ad, torch, np, workloads, args):
     dt, it, st = run_once(ad, torch, sim, wl.primaries)
     ts = sum(st["track_steps"])
     lay_m = sim.tally(ad.T_LAYER).reshape(len(wl.seeds), 50).sum(axis=0)
+    # the same run in timed mode (iterations launched one by one, HIP events around
+    # every step kernel): the step kernel's own bandwidth
+    ad.adept_set_timing(sim.ctx, True)
+    _, _, st_t = run_once(ad, torch, sim, wl.primaries)
+    ad.adept_set_timing(sim.ctx, False)
     sim.close()
+    assert st_t["track_steps"] == st["track_steps"]
     out["mixed"] = {"seconds": dt, "track_steps": ts, "track_steps_per_s": ts / dt, "iterations": it,
                     "algorithmic_GBps_run": algorithmic_bytes(st, layout[0], 1) / dt / 1e9,
-                    "primaries_per_s": len(wl.primaries) / dt, "divergent_wave_fraction": st["waves_divergent"] / max(st["waves"], 1)}
+                    "primaries_per_s": len(wl.primaries) / dt,
+                    "divergent_wave_fraction": st["waves_divergent"] / max(st["waves"], 1),
+                    "roofline": kernel_roofline(st_t, layout[0], 1)}
     # the FP64 sparse single buffer (the paper's baseline structure), same admission
     sp = ad.Sim(0, 0, ad.FP64, C, 1, seeds=wl.seeds, admission=(0.8, kappa), launch=launch)
     dt2, it2, st2 = run_once(ad, torch, sp, wl.primaries)
@@ -280,24 +353,39 @@ def batched_profile(ad, torch, np, workloads):
 
 
 def segmented_section(ad, torch, np, workloads):
+    """10^6 e- of 10 GeV in 1000 events with 100x100 cells per layer, mixed, dense SoA,
+    admission: wall-clock rate, step-kernel roofline (timed run), and the per-layer
+    and per-cell deposit error against the same workload in FP64 (the FP64 GPU path
+    is bit-exact with the FP64 oracle per track)."""
     wl = workloads.segmented_1000_events()
     C = 1 << 28
     kappa = kappa_per_gev()
-    sim = ad.Sim(ad.DENSE_DOUBLE, ad.MAP_SOA, ad.MIXED, C, 64, seeds=wl.seeds, scoring=(100, 100, 4.0),
-                 admission=(0.8, kappa), launch={"block": 1024, "graph_iters": 32})
-    ad.adept_set_timing(sim.ctx, True)
-    dt, it, st = run_once(ad, torch, sim, wl.primaries)
-    cells = sim.tally(ad.T_CELLS)
-    lay = sim.tally(ad.T_LAYER).reshape(len(wl.seeds), 50).sum(axis=0)
-    sim.close()
-    alg = algorithmic_bytes(st, 1, 1)
-    ts = sum(st["track_steps"])
-    return {"workload": wl.description + ", 100x100 cells of 4 mm per layer", "capacity_per_type": C,
-            "seconds": dt, "track_steps_per_s": ts / dt, "iterations": it,
-            "step_kernel_GBps": alg / (st["step_kernel_ms"] / 1e3) / 1e9,
-            "frac_of_hbm_peak": alg / (st["step_kernel_ms"] / 1e3) / 1e9 / PEAK_HBM_GBS,
-            "divergent_wave_fraction": st["waves_divergent"] / max(st["waves"], 1),
-            "cells_sum_over_layer_sum": float(cells.sum() / lay.sum())}
+    res = {"workload": wl.description + ", 100x100 cells of 4 mm per layer", "capacity_per_type": C}
+    tallies = {}
+    for prec in (ad.MIXED, ad.FP64):
+        sim = ad.Sim(ad.DENSE_DOUBLE, ad.MAP_SOA, prec, C, 64, seeds=wl.seeds, scoring=(100, 100, 4.0),
+                     admission=(0.8, kappa), launch={"block": 1024, "graph_iters": 32})
+        dt, it, st = run_once(ad, torch, sim, wl.primaries)
+        tallies[prec] = (sim.tally(ad.T_LAYER).reshape(len(wl.seeds), 50).sum(axis=0), sim.tally(ad.T_CELLS))
+        rec = {"seconds": dt, "track_steps_per_s": sum(st["track_steps"]) / dt, "iterations": it,
+               "divergent_wave_fraction": st["waves_divergent"] / max(st["waves"], 1)}
+        if prec == ad.MIXED:
+            ad.adept_set_timing(sim.ctx, True)
+            _, _, st_t = run_once(ad, torch, sim, wl.primaries)
+            assert st_t["track_steps"] == st["track_steps"]
+            rec["roofline"] = kernel_roofline(st_t, 1, 1)
+        sim.close()
+        res["mixed" if prec == ad.MIXED else "fp64"] = rec
+    (lm, cm), (lf, cf) = tallies[ad.MIXED], tallies[ad.FP64]
+    rel = np.abs(lm - lf) / lf
+    big = cf > 1e-6 * cf.sum()
+    res["edep_rel_error_mixed_vs_fp64"] = {
+        "per_layer_max": float(rel.max()), "per_layer_max_over_layers_above_1e-3_of_total":
+            float(rel[lf > 1e-3 * lf.sum()].max()), "total": float(abs(lm.sum() - lf.sum()) / lf.sum()),
+        "per_cell_max_over_cells_above_1e-6_of_total": float((np.abs(cm - cf)[big] / cf[big]).max()),
+        "cells_sum_over_layer_sum_mixed": float(cm.sum() / lm.sum())}
+    res["speedup_mixed_vs_fp64"] = res["fp64"]["seconds"] / res["mixed"]["seconds"]
+    return res
 
 
 def layout_study(ad, torch, np, workloads):
@@ -308,7 +396,9 @@ def layout_study(ad, torch, np, workloads):
     wl = workloads.showers_10ke_10gev()
     C = 1 << 22
     dev = torch.from_numpy(wl.primaries.view(np.uint8).copy()).cuda()
-    res = {"workload": wl.description, "precision": "FP64", "timings": {}}
+    res = {"workload": wl.description, "precision": "FP64", "timings": {},
+           "note": "the active set peaks near 10^6 tracks (about 0.1 GB per buffer), largely inside the 256 MB "
+                   "Infinity Cache: the rooflines here are not HBM measurements"}
     for name, (s, m, n) in {"sparse AoS": (0, 0, 1), "dense AoS": (1, 0, 1), "dense SoA": (1, 1, 1),
                             "dense AoSoA-64": (1, 2, 64)}.items():
         sim = ad.Sim(s, m, ad.FP64, C, n, seeds=wl.seeds, launch={"block": 1024, "graph_iters": 32})
@@ -317,8 +407,11 @@ def layout_study(ad, torch, np, workloads):
             dt, it, st = run_once(ad, torch, sim, wl.primaries, dev)
             if r:
                 best = min(best, dt)
+        ad.adept_set_timing(sim.ctx, True)
+        _, _, st_t = run_once(ad, torch, sim, wl.primaries, dev)
         sim.close()
-        res["timings"][name] = {"ms": best * 1e3, "track_steps_per_s": sum(st["track_steps"]) / best}
+        res["timings"][name] = {"ms": best * 1e3, "track_steps_per_s": sum(st["track_steps"]) / best,
+                                "roofline": kernel_roofline(st_t, s, 0)}
     counts = {}
     for name, (s, m, n) in {"sparse AoS": (0, 0, 1), "dense AoS": (1, 0, 1)}.items():
         sim = ad.Sim(s, m, ad.FP64, C, n, seeds=wl.seeds, instrumented=20)
@@ -384,10 +477,18 @@ def main():
               "with no exchange until a final tally reduction, which this build does not run.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
+
+    import workloads
+
+    wl = workloads.showers_100ke_10gev(args.primaries)
+    # the CPU baseline first: the oracle's worker processes are forked before this
+    # process initialises the GPU
+    cpu = None
+    if not args.headline_only and not args.batched_profile and not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl, args.cpu_sample, 1, flip_sample=args.flip_sample)
     import torch
 
     import paper_2302_08252_amd as ad
-    import workloads
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     ad.lib()
@@ -401,7 +502,6 @@ def main():
     if args.batched_profile:
         print(json.dumps({"batched_profile": batched_profile(ad, torch, np, workloads)}), flush=True)
         return
-    wl = workloads.showers_100ke_10gev(args.primaries)
     C = 1 << args.capacity_log2
     dev_prims = torch.from_numpy(wl.primaries.view(np.uint8).copy()).cuda()
     head = time_path(ad, torch, wl, dev_prims, ad.DENSE_DOUBLE, ad.MAP_SOA, ad.MIXED, C, args, args.steps,
@@ -476,12 +576,12 @@ def main():
         }
     if not args.headline_only and not args.no_batched:
         out["batched_512_events"] = batched_section(ad, torch, np, workloads, args)
-    if args.segmented:
+    if not args.headline_only and not args.no_segmented:
         out["segmented_1000_events"] = segmented_section(ad, torch, np, workloads)
-    if args.layout_study:
+    if not args.headline_only and not args.no_layout_study:
         out["layout_study_10ke"] = layout_study(ad, torch, np, workloads)
-    if not args.headline_only and not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_sample, 1)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 
