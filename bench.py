@@ -152,6 +152,7 @@ def time_path(ad, torch, wl, dev_prims, scheme, mapping, precision, C, args, ste
             assert st["track_steps"] == per_run["track_steps"], "runs must be identical"
         per_run["step_kernel_ms"] += st["step_kernel_ms"]
         per_run["step_launches"] += st["step_launches"]
+    phase = ad.adept_phase_clocks(sim.ctx)
     layer = sim.tally(ad.T_LAYER)
     ein = sim.tally(ad.T_EIN)
     tot = (sim.tally(ad.T_DEP_CONT).sum() + sim.tally(ad.T_DEP_CUT).sum() + sim.tally(ad.T_ESCAPED).sum()
@@ -165,7 +166,7 @@ def time_path(ad, torch, wl, dev_prims, scheme, mapping, precision, C, args, ste
     return {
         "seconds": total, "ms_per_step": 1e3 * mean, "ms_min": 1e3 * min(runs), "cv": cv, "track_steps_per_run": ts,
         "track_steps_per_s": ts * steps / total, "primaries_per_s": n * steps / total,
-        "iterations": per_run["iterations"], "stats": per_run, "layer": layer, "closure": closure,
+        "iterations": per_run["iterations"], "stats": per_run, "layer": layer, "closure": closure, "phase": phase,
         "closure_without_rounding_ledger": closure_no_round,
     }
 
@@ -547,6 +548,12 @@ def main():
             "avg_step_kernel_ms": st["step_kernel_ms"] / max(st["step_launches"], 1),
         },
     }
+    if head["phase"].any():  # a library built with ADEPT_PHASE_CLOCKS=1 (ADEPT_LIBRARY)
+        names = ["load_and_step", "block_scan_and_slowest_wave", "look_back", "writes", "end_of_tile",
+                 "before_first_tile", "after_last_tile"]
+        tot = float(head["phase"].sum())
+        out["phase_clocks"] = {"fractions_of_wave_cycles": {n: float(v) / tot for n, v in zip(names, head["phase"])},
+                               "wave_cycles": int(tot), "library": ad.LIB_PATH}
     if not args.headline_only and args.fp64_steps > 0:
         f64 = time_path(ad, torch, wl, dev_prims, ad.DENSE_DOUBLE, ad.MAP_SOA, ad.FP64, C, args, args.fp64_steps,
                         1, timing=False)

@@ -294,6 +294,18 @@ adept_status adept_autotune(adept_ctx* ctx, const adept_primary* p, uint64_t n, 
  * adept_stats (step_kernel_ms, step_launches); resets the accumulators. */
 adept_status adept_set_timing(adept_ctx* ctx, int on);
 
+/* Cycle breakdown of the step kernel (a diagnostic): the shader-clock cycles
+ * every wavefront spent in each phase of its tiles, summed over all step launches
+ * since the last reset: out[0] loading and stepping the tracks, [1] the block
+ * scan with the wait for the block's slowest wavefront, [2] the decoupled
+ * look-back for the tile's offsets with its barrier, [3] writing the next
+ * buffers, [4] the end of a tile (barriers, next ticket), [5] before the first
+ * tile, [6] after the last one, [7] unused.  All zero unless the library was
+ * built with ADEPT_PHASE_CLOCKS=1 (build.py --define ADEPT_PHASE_CLOCKS=1);
+ * out is 8 host words owned by the caller.  Errors: ADEPT_E_INVALID,
+ * ADEPT_E_DEVICE. */
+adept_status adept_phase_clocks(adept_ctx* ctx, uint64_t out[8]);
+
 /* Layout autotuner: for every candidate layout, a scratch context (library-
  * owned memory, the given precision, capacity and event seeds) is tuned with
  * adept_autotune on the given primaries and the tuned configuration is timed on

@@ -12,7 +12,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libadept.so")
+# ADEPT_LIBRARY names another build of the same library (e.g. one made with
+# build.py --define ... --out ...); the default is the in-tree build.
+LIB_PATH = os.environ.get("ADEPT_LIBRARY") or os.path.join(HERE, "libadept.so")
 
 OK, E_INVALID, E_CAPACITY, E_DEVICE, E_STATE, E_NOMEM, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 SPARSE_SINGLE, DENSE_DOUBLE = 0, 1
@@ -54,7 +56,7 @@ EXPORTS = [
     "adept_line_heat", "adept_layout_map", "adept_create_typed", "adept_type_buffer_bytes",
     "adept_autotune_type_layouts",
     "adept_stats_get", "adept_dump_tracks", "adept_dump_ring", "adept_reset", "adept_autotune",
-    "adept_set_timing", "adept_autotune_layout", "adept_last_error", "adept_destroy",
+    "adept_set_timing", "adept_autotune_layout", "adept_last_error", "adept_destroy", "adept_phase_clocks",
 ]
 
 _lib = None
@@ -97,6 +99,7 @@ def lib():
         "adept_reset": (i32, [P]),
         "adept_autotune": (i32, [P, P, u64, P]),
         "adept_set_timing": (i32, [P, i32]),
+        "adept_phase_clocks": (i32, [P, P]),
         "adept_autotune_layout": (i32, [i32, u64, P, u32, u32, P, P, u64, P, P, P]),
         "adept_last_error": (ctypes.c_char_p, [P]),
         "adept_destroy": (None, [P]),
@@ -296,6 +299,13 @@ def adept_autotune(ctx, primaries):
     l = Launch()
     _check(ctx, lib().adept_autotune(ctx, _ptr(p), len(p), ctypes.byref(l)), "adept_autotune")
     return {"block": l.block, "grid": l.grid, "graph_iters": l.graph_iters}
+
+
+def adept_phase_clocks(ctx):
+    """Wave-cycles per step-kernel phase (zeros unless built with ADEPT_PHASE_CLOCKS)."""
+    out = np.zeros(8, dtype=np.uint64)
+    _check(ctx, lib().adept_phase_clocks(ctx, out.ctypes.data_as(ctypes.c_void_p)), "adept_phase_clocks")
+    return out
 
 
 def adept_set_timing(ctx, on):

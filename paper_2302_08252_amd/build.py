@@ -30,9 +30,9 @@ def _newest(paths):
 
 def build(force=True, jobs=None, verbose=False, defines=(), lib_path=LIB, build_dir=BUILD):
     """Compile every HIP translation unit and link libadept.so.  With force=False
-    an up-to-date library is kept.  defines: extra -D tuning macros
-    (ADEPT_WAVES_PER_EU, ADEPT_NT), with lib_path / build_dir for
-    a separate build."""
+    an up-to-date library is kept.  defines: extra -D tuning or diagnostic macros
+    (ADEPT_WAVES_PER_EU, ADEPT_NT, ADEPT_PHASE_CLOCKS), with lib_path / build_dir
+    for a separate build."""
     LIB_OUT, BDIR = lib_path, build_dir
     os.makedirs(BDIR, exist_ok=True)
     hdr = _newest([os.path.join(CSRC, h) for h in HEADERS])
@@ -63,4 +63,18 @@ def build(force=True, jobs=None, verbose=False, defines=(), lib_path=LIB, build_
 
 
 if __name__ == "__main__":
-    print(build(force="--if-stale" not in sys.argv, verbose="-v" in sys.argv))
+    import argparse
+
+    ap = argparse.ArgumentParser(description="build libadept.so for gfx950")
+    ap.add_argument("--if-stale", action="store_true", help="keep an up-to-date library")
+    ap.add_argument("-v", action="store_true", help="show compiler output")
+    ap.add_argument("--define", action="append", default=[], metavar="NAME=VALUE",
+                    help="tuning / diagnostic macro, e.g. ADEPT_PHASE_CLOCKS=1 (with --out)")
+    ap.add_argument("--out", default=None, help="library path of a separate build (its objects go next to it)")
+    a = ap.parse_args()
+    if a.define and not a.out:
+        ap.error("--define needs --out: the in-tree library stays the plain build")
+    out = os.path.abspath(a.out) if a.out else LIB
+    bdir = os.path.join(os.path.dirname(out), "_build") if a.out else BUILD
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    print(build(force=not a.if_stale, verbose=a.v, defines=a.define, lib_path=out, build_dir=bdir))

@@ -1348,6 +1348,18 @@ adept_status adept_autotune_type_layouts(adept_precision precision, uint64_t cap
   return ADEPT_OK;
 }
 
+adept_status adept_phase_clocks(adept_ctx* c, uint64_t out[8]) {
+  if (!c || !out) return ADEPT_E_INVALID;
+  memset(out, 0, 8 * sizeof(uint64_t));
+  if (c->state == CREATED) return ADEPT_OK;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  Ctrl h;
+  HIPCHK(hipMemcpy(&h, c->args.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+  static_assert(kPhases == 8, "adept_phase_clocks reports eight phases");
+  for (int i = 0; i < kPhases; ++i) out[i] = h.phase[i];
+  return ADEPT_OK;
+}
+
 adept_status adept_set_timing(adept_ctx* c, int on) {
   if (!c) return ADEPT_E_INVALID;
   c->timing = on ? 1 : 0;

@@ -36,6 +36,17 @@ namespace adept {
 #define ADEPT_STEP_ATTR
 #endif
 
+// Phase clocks of the step kernel (measurement only; 0 in normal builds): every
+// wavefront adds the shader-clock cycles it spends in each phase of a tile to
+// per-block LDS sums, which go to Ctrl::phase at the end of the launch.
+#ifndef ADEPT_PHASE_CLOCKS
+#define ADEPT_PHASE_CLOCKS 0
+#endif
+// Phases: 0 load + step, 1 block scan (with the wait for the block's slowest
+// wavefront), 2 look-back (with its barrier), 3 writes, 4 end of tile (barriers
+// and the next ticket), 5 before the first tile, 6 after the last tile.
+constexpr int kPhases = 8;
+
 // Blocks (= compaction tiles) of 64 to 1024 threads.  The step kernel exists in
 // two register budgets: launch bounds 256 for tiles up to 256 tracks, and 1024
 // (128 VGPRs, four waves per SIMD) for 512 and 1024: larger tiles spread the
@@ -69,6 +80,7 @@ struct Ctrl {
   unsigned int had_staged;
   unsigned long long adm_for;       // admission: iterations done + 1 when the next one's admission is decided
   unsigned long long overflow;      // set by kernels that saw an index beyond capacity
+  unsigned long long phase[kPhases];// wave-cycles per step-kernel phase (ADEPT_PHASE_CLOCKS builds)
 };
 
 // Mirror of the few values the host polls (pinned host memory).
@@ -140,6 +152,23 @@ __device__ __forceinline__ unsigned long long ld_agent(const unsigned long long*
 __device__ __forceinline__ void st_agent(unsigned long long* p, unsigned long long v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+
+// Per-wavefront phase timer (lane 0 of every wavefront; compiled out unless
+// ADEPT_PHASE_CLOCKS).
+struct PhaseTimer {
+#if ADEPT_PHASE_CLOCKS
+  unsigned long long last;
+  __device__ __forceinline__ void start() { last = __builtin_readcyclecounter(); }
+  __device__ __forceinline__ void mark(unsigned long long* acc, int phase) {
+    const unsigned long long now = __builtin_readcyclecounter();
+    if (__lane_id() == 0) atomicAdd(&acc[phase], now - last);
+    last = now;
+  }
+#else
+  __device__ __forceinline__ void start() {}
+  __device__ __forceinline__ void mark(unsigned long long*, int) {}
+#endif
+};
 
 // Cross-lane sums with DPP row shifts (no LDS permute, no per-lane addresses):
 // row_shr<K>(x) is x of lane (l - K) when that lane lies in l's row of 16, else 0.
@@ -693,6 +722,9 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
   __shared__ TallyLDS tl;
   __shared__ TallyCache<P::tally_cache_bits> tc;
   __shared__ StatLDS ss;
+  __shared__ unsigned long long ph_acc[kPhases];
+  PhaseTimer pt;
+  pt.start();
   Ctrl* c = a.ctrl;
   const uint32_t p = c->parity;
   const unsigned long long n0 = c->n[p][0], n1 = c->n[p][1], n2 = c->n[p][2];
@@ -716,6 +748,7 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
   if (lds_tally) tally_init(tl);
   else cache_init(tc);
   if (threadIdx.x == 0) ss.waves = ss.waves_div = ss.surv[0] = ss.surv[1] = ss.surv[2] = 0;
+  if (ADEPT_PHASE_CLOCKS && threadIdx.x < kPhases) ph_acc[threadIdx.x] = 0;
   __syncthreads();
   const int lane = __lane_id();
   // Tiles are claimed in ticket order when a block is ready to start one, so
@@ -723,6 +756,7 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
   if (threadIdx.x == 0)
     sh.ticket = __hip_atomic_fetch_add(&c->ticket[p], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
+  pt.mark(ph_acc, 5);
   for (;;) {
     const unsigned long long tile = sh.ticket;
     if (tile >= total) break;
@@ -799,9 +833,11 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
         if (u < TPT - 1) park(pk, threadIdx.x, t, cr, surv, valid, aux);
       }
     }
+    pt.mark(ph_acc, 0);
     uint32_t lex[NS];
     unsigned long long aggw[(NS + 2) / 3];
     block_scan<NS>(cnt, lex, aggw, sh);
+    pt.mark(ph_acc, 1);
     unsigned long long agg = 0;  // lane v < NV: the tile aggregate of value v
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -812,6 +848,7 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
     }
     lookback<NV>(a.desc[p], tile, agg, sh, &c->overflow);
     __syncthreads();
+    pt.mark(ph_acc, 2);
     if (tile == total - 1 && threadIdx.x < NV)
       c->tot[p][threadIdx.x] = sat_add(sh.tile_excl[threadIdx.x], sh.tile_agg[threadIdx.x]);
 
@@ -896,6 +933,7 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
         if (valid) emit(u, t, cr, surv, aux);
       }
     }
+    pt.mark(ph_acc, 3);
     // Every read of this tile's LDS state is done.  The next ticket is taken only
     // now, when the block can start on it at once: a tile claimed while its block
     // is still writing holds up the look-back of every later tile.
@@ -903,10 +941,16 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
     if (threadIdx.x == 0)
       sh.ticket = __hip_atomic_fetch_add(&c->ticket[p], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
+    pt.mark(ph_acc, 4);
   }
   if (lds_tally) flush(a, tl);
   else cache_flush(a, tc);
   __syncthreads();
+  pt.mark(ph_acc, 6);
+  if (ADEPT_PHASE_CLOCKS) {
+    __syncthreads();
+    if (threadIdx.x < kPhases && ph_acc[threadIdx.x]) atomicAdd(&c->phase[threadIdx.x], ph_acc[threadIdx.x]);
+  }
   if (threadIdx.x == 0) {
     atomicAdd(&c->waves, ss.waves);
     if (ss.waves_div) atomicAdd(&c->waves_div, ss.waves_div);
