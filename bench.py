@@ -25,6 +25,11 @@ KERNEL_SOURCES = ["kernels.hpp", "layout.hpp", "model.hpp", "inst_dense_mixed.hi
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_step_100ke_10gev_dense_soa_mixed_pmc.md")
 
 
+def progress(msg):
+    """One line on stderr when a section of the benchmark ends."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_source_hash():
     import hashlib
 
@@ -487,6 +492,7 @@ def main():
     cpu = None
     if not args.headline_only and not args.batched_profile and not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, args.cpu_sample, 1, flip_sample=args.flip_sample)
+        progress(f"cpu baseline: {cpu['value']:.3e} track-steps/s on {cpu['cores']} cores")
     import torch
 
     import paper_2302_08252_amd as ad
@@ -507,6 +513,7 @@ def main():
     dev_prims = torch.from_numpy(wl.primaries.view(np.uint8).copy()).cuda()
     head = time_path(ad, torch, wl, dev_prims, ad.DENSE_DOUBLE, ad.MAP_SOA, ad.MIXED, C, args, args.steps,
                      args.warmup, timing=True)
+    progress(f"headline: {head['track_steps_per_s']:.3e} track-steps/s")
     st = head["stats"]
     alg = algorithmic_bytes(st, 1, 1)  # bytes of one run
     kernel_s = st["step_kernel_ms"] / 1e3
@@ -574,6 +581,7 @@ def main():
         out["fp64_sparse_aos"] = {"track_steps_per_s": sp["track_steps_per_s"], "ms_per_step": sp["ms_per_step"],
                                   "closure_error": sp["closure"], "algorithmic_GBps_run": run_gbps(sp, 0, 0),
                                   "divergent_wave_fraction": div(sp)}
+        progress("FP64 comparison paths done")
         out["algorithmic_GBps_run"] = run_gbps(head, 1, 1)
         out["speedup_vs_fp64_sparse_aos"] = sp["ms_per_step"] / head["ms_per_step"]
         out["edep_per_layer_rel_error_mixed_vs_fp64"] = {
@@ -583,10 +591,13 @@ def main():
         }
     if not args.headline_only and not args.no_batched:
         out["batched_512_events"] = batched_section(ad, torch, np, workloads, args)
+        progress("batched section done")
     if not args.headline_only and not args.no_segmented:
         out["segmented_1000_events"] = segmented_section(ad, torch, np, workloads)
+        progress("segmented section done")
     if not args.headline_only and not args.no_layout_study:
         out["layout_study_10ke"] = layout_study(ad, torch, np, workloads)
+        progress("layout study done")
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
