@@ -275,6 +275,23 @@ adept_status adept_stats_get(adept_ctx* ctx, adept_stats* out);
 adept_status adept_dump_tracks(adept_ctx* ctx, adept_particle t, adept_track_host* out, uint32_t* slots,
                                uint64_t cap, uint64_t* n);
 
+/* Bytes of the fixed device array that adept_dump_tracks_noalloc stages
+ * through (one array per GPU, held until the process ends). */
+#define ADEPT_NOALLOC_BYTES (16u << 20)
+
+/* adept_dump_tracks for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same result, staged through the library's fixed per-GPU array of
+ * ADEPT_NOALLOC_BYTES instead of buffers allocated per call.  n tracks need
+ * ceil(96 n / 256) * 256 bytes, plus 4 n when slots is not NULL; a dump that
+ * needs more fails with ADEPT_E_INVALID (and *n = the track count), nothing
+ * copied.  Allocates nothing on the device and calls no allocating routine.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (from several host threads or contexts) race and must be serialised by the
+ * caller.  Synchronous. */
+adept_status adept_dump_tracks_noalloc(adept_ctx* ctx, adept_particle t, adept_track_host* out, uint32_t* slots,
+                                       uint64_t cap, uint64_t* n);
+
 /* Sparse scheme: the free-slot ring of one type, its head and free count. */
 adept_status adept_dump_ring(adept_ctx* ctx, adept_particle t, uint32_t* ring, uint64_t cap, uint64_t* head,
                              uint64_t* count);

@@ -57,6 +57,7 @@ EXPORTS = [
     "adept_autotune_type_layouts",
     "adept_stats_get", "adept_dump_tracks", "adept_dump_ring", "adept_reset", "adept_autotune",
     "adept_set_timing", "adept_autotune_layout", "adept_last_error", "adept_destroy", "adept_phase_clocks",
+    "adept_dump_tracks_noalloc",
 ]
 
 _lib = None
@@ -95,6 +96,7 @@ def lib():
         "adept_autotune_type_layouts": (i32, [i32, u64, P, u32, u32, P, P, u64, P, P, P]),
         "adept_stats_get": (i32, [P, P]),
         "adept_dump_tracks": (i32, [P, i32, P, P, u64, P]),
+        "adept_dump_tracks_noalloc": (i32, [P, i32, P, P, u64, P]),
         "adept_dump_ring": (i32, [P, i32, P, u64, P, P]),
         "adept_reset": (i32, [P]),
         "adept_autotune": (i32, [P, P, u64, P]),
@@ -280,6 +282,17 @@ def adept_dump_tracks(ctx, ptype):
     _check(ctx, lib().adept_dump_tracks(ctx, ptype, _ptr(out), _ptr(slots), len(out), ctypes.byref(m)),
            "adept_dump_tracks")
     return out[:m.value], slots[:m.value]
+
+
+def adept_dump_tracks_noalloc(ctx, ptype, with_slots=True):
+    """adept_dump_tracks through the library's fixed device staging array."""
+    n = adept_stats_get(ctx)["counts"][ptype]
+    out = np.zeros(max(n, 1), dtype=TRACK_DTYPE)
+    slots = np.zeros(max(n, 1), dtype=np.uint32) if with_slots else None
+    m = ctypes.c_uint64()
+    _check(ctx, lib().adept_dump_tracks_noalloc(ctx, ptype, _ptr(out), _ptr(slots) if with_slots else None,
+                                                len(out), ctypes.byref(m)), "adept_dump_tracks_noalloc")
+    return out[:m.value], (slots[:m.value] if with_slots else None)
 
 
 def adept_dump_ring(ctx, ptype, capacity):

@@ -15,12 +15,20 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "kernels.hpp"
 
 using namespace adept;
+
+// Device staging of adept_dump_tracks_noalloc: one fixed array in the memory of
+// every GPU the library runs on, in place of the buffers adept_dump_tracks
+// allocates per call.  On the host its name is a stand-in, not a device
+// address: host code uses only the address hipGetSymbolAddress gives for the
+// device (noalloc_base below), taken once per device when a context is created.
+static __device__ __align__(256) unsigned char scratch[ADEPT_NOALLOC_BYTES];
 
 namespace {
 
@@ -723,6 +731,40 @@ bool valid_layout(adept_layout& layout, uint64_t capacity) {
   return true;
 }
 
+// Device address of `scratch` per device (set up once per device, with that
+// device current, by the first context created on it).
+constexpr int kMaxDevices = 64;
+std::mutex noalloc_mu;
+bool noalloc_done[kMaxDevices];
+void* noalloc_ptr[kMaxDevices];
+hipError_t noalloc_err[kMaxDevices];
+
+void noalloc_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  std::lock_guard<std::mutex> g(noalloc_mu);
+  if (noalloc_done[dev]) return;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  noalloc_err[dev] = e;
+  noalloc_ptr[dev] = e == hipSuccess ? ptr : nullptr;
+  noalloc_done[dev] = true;
+}
+
+// The staging array's device address on dev, or null with the reason in *why.
+void* noalloc_base(int dev, std::string* why) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    *why = "device index " + std::to_string(dev) + " beyond the no-alloc table";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> g(noalloc_mu);
+  if (!noalloc_done[dev]) {
+    *why = "no-alloc staging not set up on device " + std::to_string(dev);
+    return nullptr;
+  }
+  if (!noalloc_ptr[dev]) *why = std::string("hipGetSymbolAddress: ") + hipGetErrorString(noalloc_err[dev]);
+  return noalloc_ptr[dev];
+}
+
 adept_status create_ctx(adept_layout layout, const adept_layout* typed, adept_precision precision, uint64_t capacity,
                         adept_ctx** out) {
   init_ops();
@@ -743,6 +785,7 @@ adept_status create_ctx(adept_layout layout, const adept_layout* typed, adept_pr
     return ADEPT_E_DEVICE;
   }
   memset(c->mirror, 0, sizeof(HostMirror));
+  noalloc_setup(c->device);
   *out = c;
   return ADEPT_OK;
 }
@@ -1169,6 +1212,47 @@ adept_status adept_dump_tracks(adept_ctx* c, adept_particle t, adept_track_host*
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipFree(d_out));
     HIPCHK(hipFree(d_slots));
+  }
+  *n = cnt;
+  return ADEPT_OK;
+}
+
+adept_status adept_dump_tracks_noalloc(adept_ctx* c, adept_particle t, adept_track_host* out, uint32_t* slots,
+                                       uint64_t cap, uint64_t* n) {
+  if (!c || t < 0 || t > 2 || !n) return ADEPT_E_INVALID;
+  if (c->state == CREATED) {
+    *n = 0;
+    return ADEPT_OK;
+  }
+  std::string why;
+  unsigned char* base = (unsigned char*)noalloc_base(c->device, &why);
+  if (!base) return fail(c, ADEPT_E_DEVICE, why);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  Ctrl h;
+  HIPCHK(hipMemcpy(&h, c->args.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+  const unsigned long long cnt = h.n[h.parity][t];
+  if (cap < cnt || (!out && cnt)) {
+    *n = cnt;
+    return fail(c, ADEPT_E_INVALID, "dump buffer too small: need " + std::to_string(cnt));
+  }
+  // records first, then (256-byte aligned) the slot numbers
+  const unsigned long long rec_bytes = (cnt * sizeof(adept_track_host) + 255) / 256 * 256;
+  const unsigned long long need = rec_bytes + (slots ? cnt * 4 : 0);
+  if (need > ADEPT_NOALLOC_BYTES) {
+    *n = cnt;
+    return fail(c, ADEPT_E_INVALID,
+                std::to_string(cnt) + " tracks need " + std::to_string(need) + " bytes of device staging, beyond the " +
+                    std::to_string((unsigned long long)ADEPT_NOALLOC_BYTES) +
+                    " bytes of the no-alloc array: use adept_dump_tracks");
+  }
+  if (cnt) {
+    adept_track_host* d_out = (adept_track_host*)base;
+    uint32_t* d_slots = slots ? (uint32_t*)(base + rec_bytes) : nullptr;
+    ops(c).dump(c->args, t, d_out, d_slots, cnt, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(out, d_out, cnt * sizeof(adept_track_host), hipMemcpyDeviceToHost, c->stream));
+    if (slots) HIPCHK(hipMemcpyAsync(slots, d_slots, cnt * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
   }
   *n = cnt;
   return ADEPT_OK;
