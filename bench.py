@@ -78,6 +78,8 @@ def parse():
     ap.add_argument("--capacity-log2", type=int, default=25)
     ap.add_argument("--block", type=int, default=1024)
     ap.add_argument("--graph-iters", type=int, default=32)
+    ap.add_argument("--wave-tiles", type=int, default=0, choices=[0, 1],
+                    help="compaction tile of the step kernel: 0 = the block, 1 = the wavefront")
     ap.add_argument("--fp64-steps", type=int, default=2, help="timed runs of each FP64 comparison path (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=9600, help="primaries of the workload run by the oracle")
@@ -129,7 +131,7 @@ def kernel_roofline(st, scheme, precision):
 
 def time_path(ad, torch, wl, dev_prims, scheme, mapping, precision, C, args, steps, warmup, timing):
     sim = ad.Sim(scheme, mapping, precision, C, 64, seeds=wl.seeds,
-                 launch={"block": args.block, "graph_iters": args.graph_iters})
+                 launch={"block": args.block, "graph_iters": args.graph_iters, "wave_tiles": args.wave_tiles})
     n = len(wl.primaries)
     for _ in range(warmup):
         sim.reset()
@@ -536,6 +538,7 @@ def main():
                         "50-layer absorber/gap calorimeter; all primaries injected at once",
             "scheme": "dense double buffer", "layout": "SoA", "precision": "mixed",
             "capacity_per_type": C, "block": args.block, "graph_iters": args.graph_iters,
+            "wave_tiles": args.wave_tiles,
         },
         "primaries_per_s": head["primaries_per_s"],
         "timed_runs": {"ms_mean": head["ms_per_step"], "ms_min": head["ms_min"], "cv": head["cv"]},

@@ -125,10 +125,14 @@ typedef struct {
 
 /* Launch configuration (autotuner output; also settable by hand). */
 typedef struct {
-  uint32_t block;       /* threads per block = compaction tile: power of 2, 64-1024 (default 1024) */
+  uint32_t block;       /* threads per block: power of 2, 64-1024 (default 1024)  */
   uint32_t grid;        /* resident blocks (0: library default)                  */
   uint32_t graph_iters; /* iterations captured per hipGraph replay (1..256)      */
-  uint32_t pad;
+  uint32_t wave_tiles;  /* compaction granularity of the step: 0 = one tile per
+                           block (block scan, one look-back per block), 1 = one
+                           tile per wavefront (each wavefront scans and looks
+                           back on its own; no block barrier in the tile loop).
+                           Same results either way.                            */
 } adept_launch;
 
 /* Create a context (paper Sec. 2: the track data structure, one of its two

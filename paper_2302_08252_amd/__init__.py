@@ -46,7 +46,7 @@ class Stats(ctypes.Structure):
 
 class Launch(ctypes.Structure):
     _fields_ = [("block", ctypes.c_uint32), ("grid", ctypes.c_uint32), ("graph_iters", ctypes.c_uint32),
-                ("pad", ctypes.c_uint32)]
+                ("wave_tiles", ctypes.c_uint32)]
 
 
 EXPORTS = [
@@ -175,15 +175,15 @@ def adept_set_instrumented(ctx, on, last_iter):
     _check(ctx, lib().adept_set_instrumented(ctx, int(on), int(last_iter)), "adept_set_instrumented")
 
 
-def adept_set_launch(ctx, block=1024, grid=0, graph_iters=32):
-    l = Launch(block, grid, graph_iters, 0)
+def adept_set_launch(ctx, block=1024, grid=0, graph_iters=32, wave_tiles=0):
+    l = Launch(block, grid, graph_iters, int(wave_tiles))
     _check(ctx, lib().adept_set_launch(ctx, ctypes.byref(l)), "adept_set_launch")
 
 
 def adept_get_launch(ctx):
     l = Launch()
     _check(ctx, lib().adept_get_launch(ctx, ctypes.byref(l)), "adept_get_launch")
-    return {"block": l.block, "grid": l.grid, "graph_iters": l.graph_iters}
+    return {"block": l.block, "grid": l.grid, "graph_iters": l.graph_iters, "wave_tiles": l.wave_tiles}
 
 
 def adept_inject(ctx, primaries):
@@ -311,7 +311,7 @@ def adept_autotune(ctx, primaries):
     p = np.ascontiguousarray(primaries).view(PRIMARY_DTYPE)
     l = Launch()
     _check(ctx, lib().adept_autotune(ctx, _ptr(p), len(p), ctypes.byref(l)), "adept_autotune")
-    return {"block": l.block, "grid": l.grid, "graph_iters": l.graph_iters}
+    return {"block": l.block, "grid": l.grid, "graph_iters": l.graph_iters, "wave_tiles": l.wave_tiles}
 
 
 def adept_phase_clocks(ctx):
@@ -336,7 +336,7 @@ def adept_autotune_layout(precision, capacity, candidates, seeds, primaries):
                                      ctypes.byref(ms))
     _check(None, rc, "adept_autotune_layout")
     return ((best.scheme, best.mapping, best.aosoa_lanes),
-            {"block": l.block, "grid": l.grid, "graph_iters": l.graph_iters}, ms.value)
+            {"block": l.block, "grid": l.grid, "graph_iters": l.graph_iters, "wave_tiles": l.wave_tiles}, ms.value)
 
 
 def adept_autotune_type_layouts(precision, capacity, candidates, seeds, primaries):
@@ -351,7 +351,7 @@ def adept_autotune_type_layouts(precision, capacity, candidates, seeds, primarie
                                            ctypes.cast(best, ctypes.c_void_p), ctypes.byref(l), ctypes.byref(ms))
     _check(None, rc, "adept_autotune_type_layouts")
     return ([(b.mapping, b.aosoa_lanes) for b in best],
-            {"block": l.block, "grid": l.grid, "graph_iters": l.graph_iters}, ms.value)
+            {"block": l.block, "grid": l.grid, "graph_iters": l.graph_iters, "wave_tiles": l.wave_tiles}, ms.value)
 
 
 def adept_last_error(ctx):

@@ -590,7 +590,7 @@ void launch_iteration(adept_ctx* c, const KArgs& a, hipStream_t s, hipEvent_t e0
   const Ops& o = ops(c);
   if (c->adm_on) launch_inject(c, a, s, true);  // admitted by k_admit or the previous epilogue
   if (e0) (void)hipEventRecord(e0, s);
-  o.step(a, grid_of(c), c->launch.block, s);
+  o.step(a, grid_of(c), c->launch.block, (int)c->launch.wave_tiles, s);
   if (e1) (void)hipEventRecord(e1, s);
   hipLaunchKernelGGL(k_epilogue, dim3(1), dim3(64), 0, s, a);
 }
@@ -914,6 +914,7 @@ adept_status adept_set_launch(adept_ctx* c, const adept_launch* l) {
     return fail(c, ADEPT_E_INVALID, "block must be a power of two in [64, " + std::to_string(kMaxBlock) + "]");
   if (l->graph_iters < 1 || l->graph_iters > 256) return fail(c, ADEPT_E_INVALID, "graph_iters in [1, 256]");
   if (l->grid > kMaxGrid) return fail(c, ADEPT_E_INVALID, "grid above the maximum of 8192 blocks");
+  if (l->wave_tiles > 1) return fail(c, ADEPT_E_INVALID, "wave_tiles is 0 or 1");
   c->launch = *l;
   c->graph_valid = false;
   return ADEPT_OK;

@@ -960,6 +960,344 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Wavefront tiles: the same iteration with one compaction tile per wavefront
+// (TPT * 64 consecutive tracks of one type) instead of one per block.  A
+// wavefront claims its tile from the ticket counter, steps it, scans its output
+// counts with DPP, resolves the tile's global offsets by its own decoupled
+// look-back, and writes; it never waits for the other wavefronts of its block,
+// so a wavefront that polls its predecessors (asleep between polls) leaves the
+// CU's issue slots to the block's other wavefronts, which go on stepping.
+// The canonical order, and hence every slot, is the one of the block tiles.
+// ---------------------------------------------------------------------------
+
+// Decoupled look-back of one wavefront: lane v < NV holds the tile aggregate of
+// value v on entry and receives its exclusive prefix.  Same descriptor words and
+// spin bound as `lookback`; polls are spaced by s_sleep.
+template <int NV>
+__device__ __forceinline__ unsigned long long lookback_wave(unsigned long long* desc, unsigned long long tile,
+                                                            unsigned long long agg, unsigned long long* err) {
+  const int lane = __lane_id();
+  if (tile == 0) {
+    if (lane < NV) st_agent(&desc[lane], kStP | (agg << 31) | agg);
+    return 0;
+  }
+  if (lane < NV) st_agent(&desc[tile * NV + lane], kStA | agg);
+  unsigned long long acc[NV];
+  long long base[NV];
+  bool done[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    acc[v] = 0;
+    base[v] = (long long)tile - 1;
+    done[v] = false;
+  }
+  for (unsigned polls = 0;; ++polls) {
+    if (polls >= kSpinLimit) {
+      if (lane == 0) atomicOr(err, 2ull);
+      break;
+    }
+    bool all_done = true, waiting = false;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      if (done[v]) continue;
+      const long long j = base[v] - lane;
+      const unsigned long long w = j >= 0 ? ld_agent(&desc[(unsigned long long)j * NV + v]) : kStP;
+      const unsigned long long st = w >> 62;
+      const unsigned long long pm = __ballot(st == 2);
+      const unsigned long long xm = __ballot(st == 0);
+      const int fp = pm ? __ffsll((long long)pm) - 1 : 64;
+      const unsigned long long need = fp >= 63 ? ~0ull : ((2ull << fp) - 1);
+      if (xm & need) {
+        all_done = false;
+        waiting = true;
+        continue;
+      }
+      unsigned long long val = 0;
+      if (lane < fp) val = w & kSat;
+      else if (lane == fp) val = (w >> 31) & kSat;
+      acc[v] = sat_add(acc[v], wave_sum(val));
+      if (fp < 64) done[v] = true;
+      else {
+        base[v] -= 64;
+        all_done = false;
+      }
+    }
+    if (all_done) break;
+    if (waiting) __builtin_amdgcn_s_sleep(2);
+  }
+  unsigned long long ex = 0;
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+    if (v == lane) ex = acc[v];
+  if (lane < NV) st_agent(&desc[tile * NV + lane], kStP | (sat_add(ex, agg) << 31) | agg);
+  return ex;
+}
+
+// 64-bit value of lane 0, uniform.
+__device__ __forceinline__ unsigned long long first_lane_u64(unsigned long long x) {
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Writes of one stepped track: the survivor (dense: the whole record into the
+// next buffer; sparse: in place, its slot into the next list, or the freed slot
+// into the ring) and its creations.  pos(v) gives the global position of the
+// track's next output of value v and advances it (v < 3: next array / next list
+// of type v; sparse 3 + d: ring allocations of type d; 6 + d: slots freed).
+template <int SCHEME, int MAP, class P, bool INSTR, class Pos>
+__device__ __forceinline__ void emit_track(const KArgs& a, Ctrl* c, uint32_t p, int D,
+                                           const Acc<MAP, P::mixed, INSTR>& Acur, bool counting,
+                                           const Track<typename P::R>& t, const Creations<typename P::R>& cr,
+                                           bool surv, uint64_t aux, Pos&& pos) {
+  const uint32_t n_step = t.ctr - (surv ? 1u : 0u);  // a survivor leaves with the next counter
+  const int ncr = cr.n;
+  if constexpr (SCHEME == DENSE) {
+    const int bn = 1 - (int)p;
+    if (surv) {
+      const unsigned long long q = pos(D);
+      if (q < a.C) {
+        const auto An = make_acc<MAP, P, INSTR>(a, D, bn, counting);
+        store_full<MAP, P, INSTR>(An, q, t.pos, t.dir, t.E, t.nl, t.id, aux, t.seed, t.ctr, t.vol, t.event);
+      } else {
+        atomicOr(&c->overflow, 1ull);
+      }
+    }
+#pragma unroll 1
+    for (int i = 0; i < ncr; ++i) {
+      const int d = cr.type(i);
+      const unsigned long long q = pos(d);
+      if (q < a.C) write_creation<MAP, P, INSTR>(a, d, bn, q, counting, t, cr, i, n_step);
+      else atomicOr(&c->overflow, 1ull);
+    }
+  } else {
+    const uint32_t slot = (uint32_t)aux;
+    if (surv) {
+      const unsigned long long q = pos(D);
+      store_inplace<MAP, P, INSTR>(Acur, slot, t, D != GAMMA);
+      if (q < a.C) a.list[D][1 - p][q] = slot;
+    } else {
+      const unsigned long long f = pos(6 + D);
+      a.ring[D][(c->head[D] + c->count[D] + f) % a.C] = slot;
+    }
+#pragma unroll 1
+    for (int i = 0; i < ncr; ++i) {
+      const int d = cr.type(i);
+      const unsigned long long q = pos(d);
+      const unsigned long long j = pos(3 + d);
+      if (j < c->count[d] && q < a.C) {
+        const uint32_t s = a.ring[d][(c->head[d] + j) % a.C];
+        write_creation<MAP, P, INSTR>(a, d, 0, s, counting, t, cr, i, n_step);
+        a.list[d][1 - p][q] = s;
+      } else {
+        atomicOr(&c->overflow, 1ull);
+      }
+    }
+  }
+}
+
+template <int SCHEME, int MAP, class P, bool INSTR, int LB>
+__global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step_wave(const KArgs a) {
+  using R = typename P::R;
+  constexpr int NV = SCHEME == DENSE ? 3 : 9;
+  constexpr int TPT = P::tracks_per_lane(LB);
+  constexpr int NS = NV * TPT;
+  constexpr int W = (NS + 2) / 3;  // 32-bit words of three 10-bit counts
+  __shared__ Park<R, (TPT > 1)> pk;
+  __shared__ TallyLDS tl;
+  __shared__ TallyCache<P::tally_cache_bits> tc;
+  __shared__ StatLDS ss;
+  __shared__ unsigned long long ph_acc[kPhases];
+  PhaseTimer pt;
+  pt.start();
+  Ctrl* c = a.ctrl;
+  const uint32_t p = c->parity;
+  const unsigned long long n0 = c->n[p][0], n1 = c->n[p][1], n2 = c->n[p][2];
+  constexpr unsigned long long TT = 64ull * TPT;
+  const unsigned long long t0 = ceil_div(n0, TT), t1 = ceil_div(n1, TT), t2 = ceil_div(n2, TT);
+  const unsigned long long total = t0 + t1 + t2;
+  const unsigned long long T = blockDim.x;
+  const bool counting = INSTR && a.instr_on && c->iter < a.instr_last;
+  const bool lds_tally = a.n_events == 1 && !a.cells;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    c->ticket[1 - p] = 0;
+    c->ntiles[p] = total;
+  }
+  {  // clear the look-back words of the previous iteration
+    const unsigned long long prev = c->ntiles[1 - p] * NV;
+    unsigned long long* d = a.desc[1 - p];
+    for (unsigned long long i = (unsigned long long)blockIdx.x * T + threadIdx.x; i < prev;
+         i += (unsigned long long)gridDim.x * T)
+      d[i] = 0;
+  }
+  if ((unsigned long long)blockIdx.x * (T / 64) >= total) return;
+  if (lds_tally) tally_init(tl);
+  else cache_init(tc);
+  if (threadIdx.x == 0) ss.waves = ss.waves_div = ss.surv[0] = ss.surv[1] = ss.surv[2] = 0;
+  if (ADEPT_PHASE_CLOCKS && threadIdx.x < kPhases) ph_acc[threadIdx.x] = 0;
+  __syncthreads();
+  const int lane = __lane_id();
+  unsigned long long tile = 0;
+  if (lane == 0) tile = __hip_atomic_fetch_add(&c->ticket[p], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  tile = first_lane_u64(tile);
+  pt.mark(ph_acc, 5);
+  while (tile < total) {
+    int D;
+    unsigned long long lt, nD;
+    if (tile < t0) { D = ELECTRON; lt = tile; nD = n0; }
+    else if (tile < t0 + t1) { D = POSITRON; lt = tile - t0; nD = n1; }
+    else { D = GAMMA; lt = tile - t0 - t1; nD = n2; }
+    const int bcur = SCHEME == DENSE ? (int)p : 0;
+    const auto Acur = make_acc<MAP, P, INSTR>(a, D, bcur, counting);
+    uint32_t cnt[NS];
+#pragma unroll
+    for (int v = 0; v < NS; ++v) cnt[v] = 0;
+    Track<R> t;
+    Creations<R> cr;
+    bool surv = false, valid = false;
+    uint64_t aux = 0;
+#pragma unroll
+    for (int u = 0; u < TPT; ++u) {
+      const unsigned long long idx = lt * TT + (unsigned long long)u * 64 + lane;
+      valid = idx < nD;
+      cr.n = 0;
+      cr.meta = 0;
+      surv = false;
+      aux = 0;
+      Deposits dep{0.0, 0.0, 0.0, 0.0, {0.0, 0.0}};
+      int lim_code = 0;
+      uint32_t slot = 0;
+      if (valid) {
+        slot = SCHEME == DENSE ? (uint32_t)idx : a.list[D][p][idx];
+        load_track<MAP, P, INSTR>(Acur, slot, t);
+        const int v0 = t.vol;
+        surv = D == GAMMA ? step_photon<P>(t, cr, dep) : step_charged<P>(t, D, cr, dep);
+        lim_code = (surv ? 1 : 0) | (cr.n << 1);
+        book(a, lds_tally ? &tl : nullptr, lds_tally ? nullptr : &tc, t.event, v0, dep, t.pos);
+      }
+      {  // divergence diagnostic: lanes of a wavefront that disagree on the outcome
+        const unsigned long long vm = __ballot(valid);
+        if (vm) {
+          const int first = __ffsll((long long)vm) - 1;
+          const int ref = __builtin_amdgcn_readlane(lim_code, first);
+          const unsigned long long dm = __ballot(valid && lim_code != ref);
+          const unsigned long long sm = __ballot(valid && surv);
+          if (lane == first) {
+            atomicAdd(&ss.waves, 1ull);
+            if (dm) atomicAdd(&ss.waves_div, 1ull);
+            if (sm) atomicAdd(&ss.surv[D], (unsigned long long)__popcll(sm));
+          }
+        }
+      }
+      if (valid) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          uint32_t c_new = 0;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) c_new += (i < cr.n && cr.type(i) == d) ? 1u : 0u;
+          cnt[u * NV + d] = c_new + ((surv && D == d) ? 1u : 0u);
+          if (SCHEME == SPARSE) {
+            cnt[u * NV + 3 + d] = c_new;
+            cnt[u * NV + 6 + d] = (!surv && D == d) ? 1u : 0u;
+          }
+        }
+      }
+      if (SCHEME == DENSE) {
+        if (valid && surv) aux = Acur.template ld<uint64_t>(slot, 9);
+      } else {
+        aux = slot;
+      }
+      if constexpr (TPT > 1) {
+        if (u < TPT - 1) park(pk, threadIdx.x, t, cr, surv, valid, aux);
+      }
+    }
+    pt.mark(ph_acc, 0);
+    // wavefront scan of the counts, three 10-bit fields per word (a wavefront's
+    // totals stay below 2^10)
+    uint32_t lexw[W], totw[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      uint32_t x = 0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        if (3 * w + k < NS) x |= cnt[3 * w + k] << (10 * k);
+      const uint32_t inc = wave_scan(x);
+      lexw[w] = inc - x;
+      totw[w] = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+    }
+    auto field = [&](const uint32_t* words, int s) -> uint32_t { return (words[s / 3] >> (10 * (s % 3))) & 0x3FFu; };
+    unsigned long long agg = 0;  // lane v < NV: the tile aggregate of value v
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      uint32_t sum = 0;
+#pragma unroll
+      for (int u = 0; u < TPT; ++u) sum += field(totw, u * NV + v);
+      if (lane == v) agg = sum;
+    }
+    pt.mark(ph_acc, 1);
+    const unsigned long long exl = lookback_wave<NV>(a.desc[p], tile, agg, &c->overflow);
+    unsigned long long excl[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) excl[v] = lane_value(exl, v);
+    if (tile == total - 1 && lane < NV) c->tot[p][lane] = sat_add(exl, agg);
+    pt.mark(ph_acc, 2);
+    auto emit_u = [&](int u, const Track<R>& t, const Creations<R>& cr, bool surv,
+                      uint64_t aux) __attribute__((always_inline)) {
+      // running tile-local position of this track's next output of each value:
+      // the lane's earlier tracks' sub-tiles come first
+      uint32_t k[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        uint32_t b = 0;
+#pragma unroll
+        for (int w = 0; w < TPT; ++w)
+          if (w < u) b += field(totw, w * NV + v);
+        k[v] = b + field(lexw, u * NV + v);
+      }
+      auto pos = [&](int v) __attribute__((always_inline)) -> unsigned long long {
+        unsigned long long r = 0;
+#pragma unroll
+        for (int x = 0; x < NV; ++x) {
+          if (x == v) {
+            r = excl[x] + k[x];
+            k[x] += 1;
+          }
+        }
+        return r;
+      };
+      emit_track<SCHEME, MAP, P, INSTR>(a, c, p, D, Acur, counting, t, cr, surv, aux, pos);
+    };
+    if (valid) emit_u(TPT - 1, t, cr, surv, aux);
+    if constexpr (TPT > 1) {
+#pragma unroll
+      for (int u = 0; u < TPT - 1; ++u) {
+        unpark(pk, threadIdx.x, t, cr, surv, valid, aux);
+        if (valid) emit_u(u, t, cr, surv, aux);
+      }
+    }
+    pt.mark(ph_acc, 3);
+    unsigned long long nt = 0;
+    if (lane == 0) nt = __hip_atomic_fetch_add(&c->ticket[p], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    tile = first_lane_u64(nt);
+    pt.mark(ph_acc, 4);
+  }
+  if (lds_tally) flush(a, tl);
+  else cache_flush(a, tc);
+  __syncthreads();
+  pt.mark(ph_acc, 6);
+  if (ADEPT_PHASE_CLOCKS) {
+    __syncthreads();
+    if (threadIdx.x < kPhases && ph_acc[threadIdx.x]) atomicAdd(&c->phase[threadIdx.x], ph_acc[threadIdx.x]);
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(&c->waves, ss.waves);
+    if (ss.waves_div) atomicAdd(&c->waves_div, ss.waves_div);
+    for (int d = 0; d < 3; ++d)
+      if (ss.surv[d]) atomicAdd(&c->surv[d], ss.surv[d]);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Injection: primaries [inj_begin, inj_end) of the staged array pass through the
 // creation path in input order and are appended after the current tracks.
 // ---------------------------------------------------------------------------
@@ -1147,7 +1485,8 @@ __global__ void k_inflight(const KArgs a, double* out) {
 
 // Host-side table of the launchers of one (scheme, mapping, precision, instr) variant.
 struct Ops {
-  void (*step)(const KArgs&, unsigned grid, unsigned block, hipStream_t);
+  // wave: one compaction tile per wavefront (k_step_wave) instead of per block
+  void (*step)(const KArgs&, unsigned grid, unsigned block, int wave, hipStream_t);
   void (*inject)(const KArgs&, unsigned grid, unsigned block, hipStream_t);
   void (*dump)(const KArgs&, int type, adept_track_host*, uint32_t*, unsigned long long n, hipStream_t);
   void (*inflight)(const KArgs&, double*, hipStream_t);
@@ -1155,11 +1494,17 @@ struct Ops {
 
 template <int SCHEME, int MAP, class P, bool INSTR>
 struct Variant {
-  static void step(const KArgs& a, unsigned grid, unsigned block, hipStream_t s) {
-    if (block <= 256)
+  static void step(const KArgs& a, unsigned grid, unsigned block, int wave, hipStream_t s) {
+    if (wave) {
+      if (block <= 256)
+        hipLaunchKernelGGL((k_step_wave<SCHEME, MAP, P, INSTR, 256>), dim3(grid), dim3(block), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_step_wave<SCHEME, MAP, P, INSTR, 1024>), dim3(grid), dim3(block), 0, s, a);
+    } else if (block <= 256) {
       hipLaunchKernelGGL((k_step<SCHEME, MAP, P, INSTR, 256>), dim3(grid), dim3(block), 0, s, a);
-    else
+    } else {
       hipLaunchKernelGGL((k_step<SCHEME, MAP, P, INSTR, 1024>), dim3(grid), dim3(block), 0, s, a);
+    }
   }
   static void inject(const KArgs& a, unsigned grid, unsigned block, hipStream_t s) {
     hipLaunchKernelGGL((k_inject<SCHEME, MAP, P, INSTR>), dim3(grid), dim3(block), 0, s, a);

@@ -94,22 +94,31 @@ def compare_step_counters(st0, st1, o):
         assert got == list(want), (key, got, list(want))
 
 
-FULL_CASES = [  # precision, scheme, mapping, lanes, block
-    (1, 1, 1, 1, 1024),   # the headline: mixed dense SoA, two tracks per lane
-    (0, 1, 1, 1, 1024),   # its FP64 reference
-    (0, 0, 0, 1, 1024),   # the FP64 sparse AoS baseline structure
-    (1, 1, 2, 64, 1024),  # dense AoSoA-64 (the batched layout)
-    (1, 1, 1, 1, 256),    # one track per lane
-    (0, 0, 0, 1, 256),
+FULL_CASES = [  # precision, scheme, mapping, lanes, block, wave tiles
+    (1, 1, 1, 1, 1024, 0),   # mixed dense SoA, two tracks per lane, block tiles
+    (1, 1, 1, 1, 1024, 1),   # the same with wavefront tiles
+    (0, 1, 1, 1, 1024, 0),   # its FP64 reference
+    (0, 1, 1, 1, 1024, 1),
+    (0, 0, 0, 1, 1024, 0),   # the FP64 sparse AoS baseline structure
+    (0, 0, 0, 1, 1024, 1),
+    (1, 1, 2, 64, 1024, 0),  # dense AoSoA-64 (the batched layout)
+    (1, 1, 2, 64, 1024, 1),
+    (1, 1, 1, 1, 256, 0),    # one track per lane
+    (0, 0, 0, 1, 256, 0),
+    (1, 0, 1, 1, 256, 1),    # mixed sparse SoA, wavefront tiles of one track per lane
 ]
 
 
-@pytest.mark.parametrize("precision,scheme,mapping,lanes,block", FULL_CASES)
-def test_full_size_one_iteration(ad, oracle_mod, precision, scheme, mapping, lanes, block):
-    say(f"case full_size precision={precision} scheme={scheme} mapping={mapping} lanes={lanes} block={block}")
+@pytest.mark.parametrize("precision,scheme,mapping,lanes,block,wave", FULL_CASES,
+                         ids=[f"p{p}-s{s}-m{m}x{n}-b{b}-{'wavetile' if w else 'blocktile'}"
+                              for p, s, m, n, b, w in FULL_CASES])
+def test_full_size_one_iteration(ad, oracle_mod, precision, scheme, mapping, lanes, block, wave):
+    say(f"case full_size precision={precision} scheme={scheme} mapping={mapping} lanes={lanes} block={block} "
+        f"wave={wave}")
     wl = workloads.showers_100ke_10gev()
     C = 1 << 25
-    sim = ad.Sim(scheme, mapping, precision, C, lanes, seeds=wl.seeds, launch={"block": block, "graph_iters": 32})
+    sim = ad.Sim(scheme, mapping, precision, C, lanes, seeds=wl.seeds,
+                 launch={"block": block, "graph_iters": 32, "wave_tiles": wave})
     sim.inject(wl.primaries)
     assert sim.run(60) == 60
     o = oracle_mod.Oracle(scheme, precision, C, wl.seeds)
@@ -131,14 +140,15 @@ def test_full_size_one_iteration(ad, oracle_mod, precision, scheme, mapping, lan
     o.close()
 
 
-@pytest.mark.parametrize("cells", [False, True])
-def test_batched_handover_after_last_admission(ad, oracle_mod, cells):
-    say(f"case batched handover cells={cells}")
+@pytest.mark.parametrize("cells,wave", [(False, 0), (True, 0), (False, 1), (True, 1)],
+                         ids=["blocktile", "cells-blocktile", "wavetile", "cells-wavetile"])
+def test_batched_handover_after_last_admission(ad, oracle_mod, cells, wave):
+    say(f"case batched handover cells={cells} wave={wave}")
     wl = workloads.uneven_512_events()
     C = 1 << 24
     scoring = (100, 100, 4.0) if cells else None
     sim = ad.Sim(1, 2, 1, C, 64, seeds=wl.seeds, scoring=scoring, admission=(0.8, kappa()),
-                 launch={"block": 1024, "graph_iters": 16})
+                 launch={"block": 1024, "graph_iters": 16, "wave_tiles": wave})
     sim.inject(wl.primaries)
     it = 0
     while True:  # an event's input energy is booked when it is admitted

@@ -62,21 +62,25 @@ def compare_tallies(sim, o, oracle_mod, rtol=1e-12):
     assert np.all(np.abs(g - w) <= 1e-12 * o.tally(oracle_mod.T_EIN))
 
 
+@pytest.mark.parametrize("wave", [0, 1], ids=["blocktile", "wavetile"])
 @pytest.mark.parametrize("block", [64, 1024])
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("mapping,lanes", LAYOUTS)
 @pytest.mark.parametrize("scheme", SCHEMES)
-def test_iterations_bitwise(ad, oracle_mod, scheme, mapping, lanes, precision, block):
+def test_iterations_bitwise(ad, oracle_mod, scheme, mapping, lanes, precision, block, wave):
     """Primaries of 300 MeV to 3 GeV (several tiles, ragged tails): state after every
-    iteration.  Block 64 runs one track per lane; block 1024 runs two per lane under
-    the mixed policy, with a tile of 2048 tracks, so the larger workload there."""
-    say(f"case iterations_bitwise scheme={scheme} mapping={mapping} lanes={lanes} precision={precision} block={block}")
+    iteration.  Block 64 runs one track per lane; block 1024 runs two per lane, with
+    a tile of 2048 tracks (block tiles) or 128 (wave tiles), so the larger workload
+    there."""
+    say(f"case iterations_bitwise scheme={scheme} mapping={mapping} lanes={lanes} precision={precision} "
+        f"block={block} wave={wave}")
     C = 1 << 16
     n_e, e_e = (10, 300.0) if block == 64 else (40, 3000.0)
     prims = np.concatenate([workloads.primaries(n_e, workloads.ELECTRON, e_e),
                             workloads.primaries(1, workloads.POSITRON, 40.0, first_id=n_e),
                             workloads.primaries(1, workloads.GAMMA, 25.0, first_id=n_e + 1)])
-    sim = ad.Sim(scheme, mapping, precision, C, lanes, seeds=[3], launch={"block": block, "graph_iters": 8})
+    sim = ad.Sim(scheme, mapping, precision, C, lanes, seeds=[3],
+                 launch={"block": block, "graph_iters": 8, "wave_tiles": wave})
     o = oracle_mod.Oracle(scheme, precision, C, [3])
     sim.inject(prims)
     assert o.inject(prims) == 0
@@ -103,13 +107,18 @@ def test_iterations_bitwise(ad, oracle_mod, scheme, mapping, lanes, precision, b
     sim.close()
 
 
-@pytest.mark.parametrize("block", [64, 128, 256, 512, 1024])
-def test_anchor_run_graph(ad, oracle_mod, block):
+ANCHOR_LAUNCHES = [(64, 0), (128, 0), (256, 0), (512, 0), (1024, 0), (64, 1), (256, 1), (1024, 1)]
+
+
+@pytest.mark.parametrize("block,wave", ANCHOR_LAUNCHES,
+                         ids=[f"b{b}-{'wavetile' if w else 'blocktile'}" for b, w in ANCHOR_LAUNCHES])
+def test_anchor_run_graph(ad, oracle_mod, block, wave):
     """showers_100e_1gev as specified (sparse AoS FP64, 2^20 slots, 100 e- of 1 GeV, seed 1) through
     adept_run's graph replay: counts and stats exact, per-layer deposits 1e-12."""
-    say(f"case anchor_run_graph block={block}")
+    say(f"case anchor_run_graph block={block} wave={wave}")
     wl = workloads.showers_100e_1gev()
-    sim = ad.Sim(0, 0, 0, 1 << 20, 1, seeds=wl.seeds, launch={"block": block, "graph_iters": 32})
+    sim = ad.Sim(0, 0, 0, 1 << 20, 1, seeds=wl.seeds,
+                 launch={"block": block, "graph_iters": 32, "wave_tiles": wave})
     sim.inject(wl.primaries)
     it = sim.run()
     o, rc, oit = oracle_mod.run_workload(wl, oracle_mod.SPARSE, oracle_mod.FP64, 1 << 20)
