@@ -78,6 +78,7 @@ def parse():
     ap.add_argument("--capacity-log2", type=int, default=25)
     ap.add_argument("--block", type=int, default=1024)
     ap.add_argument("--graph-iters", type=int, default=32)
+    ap.add_argument("--grid", type=int, default=0, help="resident blocks of the step kernel (0: library default)")
     ap.add_argument("--wave-tiles", type=int, default=0, choices=[0, 1],
                     help="compaction tile of the step kernel: 0 = the block, 1 = the wavefront")
     ap.add_argument("--fp64-steps", type=int, default=2, help="timed runs of each FP64 comparison path (0: skip)")
@@ -131,7 +132,8 @@ def kernel_roofline(st, scheme, precision):
 
 def time_path(ad, torch, wl, dev_prims, scheme, mapping, precision, C, args, steps, warmup, timing):
     sim = ad.Sim(scheme, mapping, precision, C, 64, seeds=wl.seeds,
-                 launch={"block": args.block, "graph_iters": args.graph_iters, "wave_tiles": args.wave_tiles})
+                 launch={"block": args.block, "grid": args.grid, "graph_iters": args.graph_iters,
+                         "wave_tiles": args.wave_tiles})
     n = len(wl.primaries)
     for _ in range(warmup):
         sim.reset()

@@ -304,10 +304,12 @@ adept_status adept_dump_ring(adept_ctx* ctx, adept_particle t, uint32_t* ring, u
  * counters, staged primaries) without reallocating. */
 adept_status adept_reset(adept_ctx* ctx);
 
-/* Pick the launch configuration (block size = compaction tile, grid, graph
- * iterations) for this context by timing runs of the given primaries on
- * scratch state; the context is reset afterwards.  Ties go to the smaller
- * block.  result (nullable) receives the choice. */
+/* Pick the launch configuration (block size, graph iterations and the
+ * compaction granularity: block or wavefront tiles) for this context by timing
+ * runs of the given primaries on scratch state; the context is reset
+ * afterwards.  Candidates are tried block tiles first, smaller blocks first; a
+ * later candidate wins only if it is 2% faster.  result (nullable) receives
+ * the choice. */
 adept_status adept_autotune(adept_ctx* ctx, const adept_primary* p, uint64_t n, adept_launch* result);
 
 /* Timed mode for measurements: adept_run launches iterations one by one with

@@ -1299,9 +1299,10 @@ adept_status adept_autotune(adept_ctx* c, const adept_primary* p, uint64_t n, ad
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
+  for (uint32_t w = 0; w < 2; ++w)  // compaction tile: the block, then the wavefront
   for (uint32_t b : blocks)
     for (uint32_t k : ks) {
-      adept_launch l{b, 0, k, 0};
+      adept_launch l{b, 0, k, w};
       adept_set_launch(c, &l);
       float ms = 0.f;
       for (int rep = 0; rep < 2; ++rep) {  // the first repetition warms up
@@ -1316,7 +1317,7 @@ adept_status adept_autotune(adept_ctx* c, const adept_primary* p, uint64_t n, ad
         if (rc) break;
       }
       if (rc) break;
-      if (ms < best_ms * 0.98f) {  // a smaller block wins unless the larger is 2% faster
+      if (ms < best_ms * 0.98f) {  // an earlier candidate wins unless a later one is 2% faster
         best_ms = ms;
         best = l;
       }

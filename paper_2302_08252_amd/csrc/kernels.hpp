@@ -1040,6 +1040,62 @@ __device__ __forceinline__ unsigned long long first_lane_u64(unsigned long long 
   return ((unsigned long long)hi << 32) | lo;
 }
 
+// Tile tickets of the wavefront-tile kernel.  A device-scope atomic on one
+// address completes only some tens of millions of times per second, fewer than
+// the wavefront tiles a launch gets through, so the block claims kBatch
+// consecutive tiles per atomic and hands them to its wavefronts in claim order
+// through LDS.  The wavefront that opens batch j (claim index kBatch j) takes it from
+// the device counter; the others wait for its base in ring entry j mod kRing.
+// An entry is reused only after every claim of the batch it held was served.
+#ifndef ADEPT_WAVE_BATCH
+#define ADEPT_WAVE_BATCH 16
+#endif
+constexpr unsigned kBatch = ADEPT_WAVE_BATCH, kRing = 4;
+struct WaveTickets {
+  unsigned int claims;
+  unsigned int gen[kRing];      // batch number + 1 of the base the entry holds
+  unsigned int served[kRing];   // claims of that batch that have read it
+  unsigned long long base[kRing];
+};
+
+__device__ __forceinline__ void tickets_init(WaveTickets& wt) {
+  if (threadIdx.x == 0) {
+    wt.claims = 0;
+    for (unsigned e = 0; e < kRing; ++e) {
+      wt.gen[e] = 0;
+      wt.served[e] = 0;
+      wt.base[e] = 0;
+    }
+  }
+}
+
+__device__ __forceinline__ unsigned long long claim_wave_tile(WaveTickets& wt, unsigned long long* ticket) {
+  const int lane = __lane_id();
+  unsigned k = 0;
+  if (lane == 0) k = atomicAdd(&wt.claims, 1u);
+  k = (unsigned)__builtin_amdgcn_readfirstlane((int)k);
+  const unsigned j = k / kBatch, slot = k % kBatch, e = j % kRing;
+  if (slot == 0) {
+    if (j >= kRing)
+      while (__hip_atomic_load(&wt.served[e], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < kBatch)
+        __builtin_amdgcn_s_sleep(1);
+    unsigned long long b = 0;
+    if (lane == 0) b = __hip_atomic_fetch_add(ticket, (unsigned long long)kBatch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    b = first_lane_u64(b);
+    if (lane == 0) {
+      wt.base[e] = b;
+      wt.served[e] = 0;
+      __hip_atomic_store(&wt.gen[e], j + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+  } else {
+    while (__hip_atomic_load(&wt.gen[e], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != j + 1)
+      __builtin_amdgcn_s_sleep(1);
+  }
+  const unsigned long long b = first_lane_u64(wt.base[e]);
+  if (lane == 0) __hip_atomic_fetch_add(&wt.served[e], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+  return b + slot;
+}
+
 // Writes of one stepped track: the survivor (dense: the whole record into the
 // next buffer; sparse: in place, its slot into the next list, or the freed slot
 // into the ring) and its creations.  pos(v) gives the global position of the
@@ -1107,6 +1163,7 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step_wave(const KArgs a)
   __shared__ TallyLDS tl;
   __shared__ TallyCache<P::tally_cache_bits> tc;
   __shared__ StatLDS ss;
+  __shared__ WaveTickets wt;
   __shared__ unsigned long long ph_acc[kPhases];
   PhaseTimer pt;
   pt.start();
@@ -1134,12 +1191,11 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step_wave(const KArgs a)
   if (lds_tally) tally_init(tl);
   else cache_init(tc);
   if (threadIdx.x == 0) ss.waves = ss.waves_div = ss.surv[0] = ss.surv[1] = ss.surv[2] = 0;
+  tickets_init(wt);
   if (ADEPT_PHASE_CLOCKS && threadIdx.x < kPhases) ph_acc[threadIdx.x] = 0;
   __syncthreads();
   const int lane = __lane_id();
-  unsigned long long tile = 0;
-  if (lane == 0) tile = __hip_atomic_fetch_add(&c->ticket[p], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  tile = first_lane_u64(tile);
+  unsigned long long tile = claim_wave_tile(wt, &c->ticket[p]);
   pt.mark(ph_acc, 5);
   while (tile < total) {
     int D;
@@ -1276,9 +1332,7 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step_wave(const KArgs a)
       }
     }
     pt.mark(ph_acc, 3);
-    unsigned long long nt = 0;
-    if (lane == 0) nt = __hip_atomic_fetch_add(&c->ticket[p], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    tile = first_lane_u64(nt);
+    tile = claim_wave_tile(wt, &c->ticket[p]);
     pt.mark(ph_acc, 4);
   }
   if (lds_tally) flush(a, tl);
