@@ -95,6 +95,12 @@ def parse():
                     help="skip showers_10ke_10gev in the paper's four layouts (timings and access counts)")
     ap.add_argument("--flip-sample", type=int, default=512,
                     help="primaries whose showers the oracle runs in both precision policies (flip count)")
+    ap.add_argument("--line-check", choices=["sparse-aos", "dense-aos", "dense-soa"], default=None,
+                    help="showers_10ke_10gev, FP64: injection + 20 iterations uninstrumented (the dispatches a "
+                         "counter run measures), then the same instrumented, printing the cache-line model of "
+                         "the bytes moved")
+    ap.add_argument("--pmc-summary", nargs="+", default=None, metavar="CSV",
+                    help="sum rocprofv3 counter CSVs per kernel and counter (no GPU use)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device to device (a plain copy of known size for scaling counters)")
     return ap.parse_args()
@@ -362,6 +368,69 @@ def batched_profile(ad, torch, np, workloads):
     return {"workload": wl.description, "layout": "dense AoSoA-64, mixed", "runs": runs}
 
 
+LINE_LAYOUTS = {"sparse-aos": (0, 0, 1), "dense-aos": (1, 0, 1), "dense-soa": (1, 1, 1)}
+
+
+def line_model(ad, np, sim, scheme):
+    """Bytes the cache-line model says move: every 128-byte line of every track
+    buffer moves once per access of its most accessed 4-byte word (heatmap of an
+    instrumented run); bytes used = 4 x the word counts."""
+    used = moved = 0
+    for t in range(3):
+        for b in range(2 if scheme else 1):
+            words = sim.access_counts(t, b, heat=True)[2].astype(np.uint64)
+            words = np.concatenate([words, np.zeros(-len(words) % 32, dtype=np.uint64)]).reshape(-1, 32)
+            used += 4 * int(words.sum())
+            moved += 128 * int(words.max(axis=1).sum())
+    return used, moved
+
+
+def line_check(ad, torch, np, workloads, which):
+    """showers_10ke_10gev in FP64: injection and 20 iterations without instrumentation
+    (k_step / k_inject launches with INSTR = false: what a counter run sums), then the
+    same window instrumented for the cache-line model of the track-buffer bytes."""
+    wl = workloads.showers_10ke_10gev()
+    s, m, n = LINE_LAYOUTS[which]
+    C = 1 << 22
+    sim = ad.Sim(s, m, ad.FP64, C, n, seeds=wl.seeds, launch={"block": 1024, "graph_iters": 20})
+    sim.inject(wl.primaries)
+    assert sim.run(20) == 20
+    st = sim.stats()
+    sim.close()
+    sim = ad.Sim(s, m, ad.FP64, C, n, seeds=wl.seeds, instrumented=20, launch={"block": 1024, "graph_iters": 20})
+    sim.inject(wl.primaries)
+    assert sim.run(20) == 20
+    used, moved = line_model(ad, np, sim, s)
+    sim.close()
+    return {"workload": wl.description, "layout": which, "precision": "FP64", "iterations": 20,
+            "track_steps": sum(st["track_steps"]), "line_model_bytes_moved": moved, "bytes_used": used,
+            "algorithmic_step_bytes": algorithmic_bytes(st, s, 0)}
+
+
+def kernel_base_name(name):
+    """A kernel's name without its trailing argument list."""
+    if name.endswith(")"):
+        depth = 0
+        for i in range(len(name) - 1, -1, -1):
+            depth += {")": 1, "(": -1}.get(name[i], 0)
+            if depth == 0:
+                return name[:i]
+    return name
+
+
+def pmc_summary(paths):
+    """Per (kernel, counter) sums over the dispatches of rocprofv3 counter CSVs."""
+    import csv
+    out = {}
+    for path in paths:
+        for r in csv.DictReader(open(path)):
+            key = f"{kernel_base_name(r['Kernel_Name'])} | {r['Counter_Name']}"
+            e = out.setdefault(key, {"sum": 0.0, "dispatches": 0})
+            e["sum"] += float(r["Counter_Value"])
+            e["dispatches"] += 1
+    return out
+
+
 def segmented_section(ad, torch, np, workloads):
     """10^6 e- of 10 GeV in 1000 events with 100x100 cells per layer, mixed, dense SoA,
     admission: wall-clock rate, step-kernel roofline (timed run), and the per-layer
@@ -482,6 +551,9 @@ def layout_study(ad, torch, np, workloads):
 
 def main():
     args = parse()
+    if args.pmc_summary:
+        print(json.dumps(pmc_summary(args.pmc_summary), indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the transport path shards by events "
               "with no exchange until a final tally reduction, which this build does not run.", file=sys.stderr)
@@ -494,7 +566,7 @@ def main():
     # the CPU baseline first: the oracle's worker processes are forked before this
     # process initialises the GPU
     cpu = None
-    if not args.headline_only and not args.batched_profile and not args.no_cpu_baseline:
+    if not args.headline_only and not args.batched_profile and not args.line_check and not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, args.cpu_sample, 1, flip_sample=args.flip_sample)
         progress(f"cpu baseline: {cpu['value']:.3e} track-steps/s on {cpu['cores']} cores")
     import torch
@@ -512,6 +584,9 @@ def main():
         del src, dst
     if args.batched_profile:
         print(json.dumps({"batched_profile": batched_profile(ad, torch, np, workloads)}), flush=True)
+        return
+    if args.line_check:
+        print(json.dumps({"line_check": line_check(ad, torch, np, workloads, args.line_check)}), flush=True)
         return
     C = 1 << args.capacity_log2
     dev_prims = torch.from_numpy(wl.primaries.view(np.uint8).copy()).cuda()
