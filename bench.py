@@ -141,10 +141,13 @@ def time_path(ad, torch, wl, dev_prims, scheme, mapping, precision, C, args, ste
                  launch={"block": args.block, "grid": args.grid, "graph_iters": args.graph_iters,
                          "wave_tiles": args.wave_tiles})
     n = len(wl.primaries)
-    for _ in range(warmup):
+    for _ in range(max(warmup, 1)):  # the warm-up run also counts the lane-weighted divergence
         sim.reset()
         ad.adept_inject_device(sim.ctx, dev_prims.data_ptr(), n)
         sim.run()
+    w = sim.stats()
+    off_mode = w["off_mode"] / max(sum(w["track_steps"]), 1)
+    ad.adept_set_divergence_count(sim.ctx, False)  # timed runs leave the diagnostic out (about 1%)
     total = 0.0
     runs = []
     per_run = None
@@ -182,6 +185,7 @@ def time_path(ad, torch, wl, dev_prims, scheme, mapping, precision, C, args, ste
         "seconds": total, "ms_per_step": 1e3 * mean, "ms_min": 1e3 * min(runs), "cv": cv, "track_steps_per_run": ts,
         "track_steps_per_s": ts * steps / total, "primaries_per_s": n * steps / total,
         "iterations": per_run["iterations"], "stats": per_run, "layer": layer, "closure": closure, "phase": phase,
+        "lanes_off_mode_fraction": off_mode,
         "closure_without_rounding_ledger": closure_no_round,
     }
 
@@ -309,11 +313,15 @@ def batched_section(ad, torch, np, workloads, args):
     cands = [(1, 0, 1), (1, 1, 1), (1, 2, 16), (1, 2, 64), (1, 2, 256)]
     sample = wl.primaries[wl.primaries["event"] < 64]  # ~64k primaries: peak below 1e7 photons < 2^24
     layout, launch, _ = ad.adept_autotune_layout(ad.MIXED, 1 << 24, cands, wl.seeds[:64], sample)
+    progress(f"batched: autotuned layout {layout}, launch {launch}")
     out = {"workload": wl.description, "capacity_per_type": C, "admission": {"alpha": 0.8, "kappa_per_GeV": kappa},
            "autotuned": {"layout": {"scheme": "dense" if layout[0] else "sparse",
                                     "mapping": ["AoS", "SoA", "AoSoA"][layout[1]], "lanes": layout[2]},
                          "launch": launch, "tuning_sample": "events 0-63, capacity 2^24"}}
     sim = ad.Sim(layout[0], layout[1], ad.MIXED, C, layout[2], seeds=wl.seeds, admission=(0.8, kappa), launch=launch)
+    _, _, st_w = run_once(ad, torch, sim, wl.primaries)  # warm-up, with the lane-weighted divergence count
+    progress("batched: warm-up run done")
+    ad.adept_set_divergence_count(sim.ctx, False)
     dt, it, st = run_once(ad, torch, sim, wl.primaries)
     ts = sum(st["track_steps"])
     lay_m = sim.tally(ad.T_LAYER).reshape(len(wl.seeds), 50).sum(axis=0)
@@ -328,16 +336,19 @@ def batched_section(ad, torch, np, workloads, args):
                     "algorithmic_GBps_run": algorithmic_bytes(st, layout[0], 1) / dt / 1e9,
                     "primaries_per_s": len(wl.primaries) / dt,
                     "divergent_wave_fraction": st["waves_divergent"] / max(st["waves"], 1),
+                    "lanes_off_mode_fraction": st_w["off_mode"] / max(sum(st_w["track_steps"]), 1),
                     "roofline": kernel_roofline(st_t, layout[0], 1)}
     # the FP64 sparse single buffer (the paper's baseline structure), same admission
     sp = ad.Sim(0, 0, ad.FP64, C, 1, seeds=wl.seeds, admission=(0.8, kappa), launch=launch)
     dt2, it2, st2 = run_once(ad, torch, sp, wl.primaries)
+    progress("batched: FP64 sparse AoS run done")
     lay_f = sp.tally(ad.T_LAYER).reshape(len(wl.seeds), 50).sum(axis=0)
     sp.close()
     ts2 = sum(st2["track_steps"])
     out["fp64_sparse_aos"] = {"seconds": dt2, "track_steps_per_s": ts2 / dt2,
                               "algorithmic_GBps_run": algorithmic_bytes(st2, 0, 0) / dt2 / 1e9,
-                              "divergent_wave_fraction": st2["waves_divergent"] / max(st2["waves"], 1)}
+                              "divergent_wave_fraction": st2["waves_divergent"] / max(st2["waves"], 1),
+                              "lanes_off_mode_fraction": st2["off_mode"] / max(sum(st2["track_steps"]), 1)}
     out["speedup_vs_fp64_sparse_aos"] = dt2 / dt
     rel = np.abs(lay_m - lay_f) / lay_f
     out["edep_per_layer_rel_error_mixed_vs_fp64"] = {"max": float(rel.max()),
@@ -445,9 +456,11 @@ def segmented_section(ad, torch, np, workloads):
         sim = ad.Sim(ad.DENSE_DOUBLE, ad.MAP_SOA, prec, C, 64, seeds=wl.seeds, scoring=(100, 100, 4.0),
                      admission=(0.8, kappa), launch={"block": 1024, "graph_iters": 32})
         dt, it, st = run_once(ad, torch, sim, wl.primaries)
+        progress(f"segmented: {'mixed' if prec == ad.MIXED else 'FP64'} run done")
         tallies[prec] = (sim.tally(ad.T_LAYER).reshape(len(wl.seeds), 50).sum(axis=0), sim.tally(ad.T_CELLS))
         rec = {"seconds": dt, "track_steps_per_s": sum(st["track_steps"]) / dt, "iterations": it,
-               "divergent_wave_fraction": st["waves_divergent"] / max(st["waves"], 1)}
+               "divergent_wave_fraction": st["waves_divergent"] / max(st["waves"], 1),
+               "lanes_off_mode_fraction": st["off_mode"] / max(sum(st["track_steps"]), 1)}
         if prec == ad.MIXED:
             ad.adept_set_timing(sim.ctx, True)
             _, _, st_t = run_once(ad, torch, sim, wl.primaries)
@@ -622,6 +635,7 @@ def main():
         "track_steps_per_run": head["track_steps_per_run"],
         "iterations_per_run": head["iterations"],
         "divergent_wave_fraction": st["waves_divergent"] / max(st["waves"], 1),
+        "lanes_off_mode_fraction": head["lanes_off_mode_fraction"],
         "divergence_rate_rocprof": (1.0 - measured_lane_use() / 64.0) if measured_lane_use() else None,
         "closure_error": head["closure"],
         "roofline": {
@@ -653,14 +667,15 @@ def main():
             return algorithmic_bytes(r["stats"], scheme, precision) / (r["ms_per_step"] * 1e-3) / 1e9
 
         def div(r):
-            return r["stats"]["waves_divergent"] / max(r["stats"]["waves"], 1)
+            return {"waves_with_disagreeing_lanes": r["stats"]["waves_divergent"] / max(r["stats"]["waves"], 1),
+                    "lanes_off_mode": r["lanes_off_mode_fraction"]}
 
         out["fp64_dense_soa"] = {"track_steps_per_s": f64["track_steps_per_s"], "ms_per_step": f64["ms_per_step"],
                                  "closure_error": f64["closure"], "algorithmic_GBps_run": run_gbps(f64, 1, 0),
-                                 "divergent_wave_fraction": div(f64)}
+                                 "divergence": div(f64)}
         out["fp64_sparse_aos"] = {"track_steps_per_s": sp["track_steps_per_s"], "ms_per_step": sp["ms_per_step"],
                                   "closure_error": sp["closure"], "algorithmic_GBps_run": run_gbps(sp, 0, 0),
-                                  "divergent_wave_fraction": div(sp)}
+                                  "divergence": div(sp)}
         progress("FP64 comparison paths done")
         out["algorithmic_GBps_run"] = run_gbps(head, 1, 1)
         out["speedup_vs_fp64_sparse_aos"] = sp["ms_per_step"] / head["ms_per_step"]

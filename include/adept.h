@@ -119,6 +119,9 @@ typedef struct {
   uint64_t waves;            /* wavefronts that stepped tracks                       */
   uint64_t waves_divergent;  /* ... whose lanes disagreed on the step limiter or the
                                 interaction outcome (divergence diagnostic)          */
+  uint64_t off_mode;         /* divergence diagnostic: track-steps whose outcome (survived?,
+                                buffered creations) differs from the most common outcome
+                                of their wavefront (64 consecutive sources of one type)  */
   int32_t status;            /* ADEPT_OK or the latched error                        */
   int32_t pad;
 } adept_stats;
@@ -305,12 +308,17 @@ adept_status adept_dump_ring(adept_ctx* ctx, adept_particle t, uint32_t* ring, u
 adept_status adept_reset(adept_ctx* ctx);
 
 /* Pick the launch configuration (block size, graph iterations and the
- * compaction granularity: block or wavefront tiles) for this context by timing
- * runs of the given primaries on scratch state; the context is reset
- * afterwards.  Candidates are tried block tiles first, smaller blocks first; a
+ * compaction granularity: block tiles of 64-1024 threads, or wavefront tiles
+ * in blocks of 1024) for this context by timing runs of the given primaries on
+ * scratch state; the context is reset afterwards.  Candidates are tried block tiles first, smaller blocks first; a
  * later candidate wins only if it is 2% faster.  result (nullable) receives
  * the choice. */
 adept_status adept_autotune(adept_ctx* ctx, const adept_primary* p, uint64_t n, adept_launch* result);
+
+/* The lane-weighted divergence diagnostic (adept_stats.off_mode), on by default;
+ * counting it costs about 1% of the step kernel, so timed runs may switch it
+ * off.  Takes effect from the next iteration. */
+adept_status adept_set_divergence_count(adept_ctx* ctx, int on);
 
 /* Timed mode for measurements: adept_run launches iterations one by one with
  * HIP events around every step kernel and accumulates their durations into

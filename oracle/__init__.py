@@ -69,6 +69,7 @@ class Ledger(ctypes.Structure):
         ("n_annihilation", ctypes.c_uint64),
         ("survivors", ctypes.c_uint64 * 3),
         ("outputs", ctypes.c_uint64 * 3),
+        ("off_mode", ctypes.c_uint64),
     ]
 
 

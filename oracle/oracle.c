@@ -1234,6 +1234,7 @@ int or_step(or_sim *S, uint64_t next_counts[3]) {
   /* pass 1: step every source in canonical order, collect outputs */
   for (int D = 0; D < 3; ++D) {
     const int b = S->scheme == OR_DENSE ? S->cur[D] : 0;
+    uint64_t group[8] = {0, 0, 0, 0, 0, 0, 0, 0}; /* outcomes in the current group of 64 */
     for (uint64_t i = 0; i < S->n[D]; ++i) {
       const uint32_t slot = S->scheme == OR_DENSE ? (uint32_t)i : S->list_cur[D][i];
       or_track trk = S->buf[D][b][slot];
@@ -1241,6 +1242,16 @@ int or_step(or_sim *S, uint64_t next_counts[3]) {
       creations cr;
       const int surv = step_track(S, D, &trk, &cr);
       S->steps[D] += 1;
+      group[(surv ? 1 : 0) | (cr.n << 1)] += 1;
+      if ((i & 63) == 63 || i + 1 == S->n[D]) {
+        uint64_t all = 0, most = 0;
+        for (int k = 0; k < 8; ++k) {
+          all += group[k];
+          if (group[k] > most) most = group[k];
+          group[k] = 0;
+        }
+        S->led.off_mode += all - most;
+      }
       if (surv) {
         S->led.survivors[D] += 1;
         if (count_on && S->scheme == OR_DENSE) count_leaf(S, D, b, slot, 9, 0);

@@ -90,6 +90,10 @@ typedef struct {
   uint64_t n_brem, n_pair, n_compton, n_annihilation;  /* interactions                */
   uint64_t survivors[3];  /* source tracks that survived their step (all iterations)  */
   uint64_t outputs[3];    /* tracks written into the next buffers (all iterations)    */
+  uint64_t off_mode;      /* divergence diagnostic: sources whose outcome (survived?,
+                             buffered creations) differs from the most common outcome
+                             of their group of 64 consecutive sources of one type in
+                             current order (the tracks one wavefront steps together) */
 } or_ledger;
 
 typedef struct or_sim or_sim;

@@ -41,7 +41,8 @@ class Stats(ctypes.Structure):
                 ("counts", ctypes.c_uint64 * 3), ("error_iter", ctypes.c_uint64),
                 ("survivors", ctypes.c_uint64 * 3), ("outputs", ctypes.c_uint64 * 3),
                 ("step_kernel_ms", ctypes.c_double), ("step_launches", ctypes.c_uint64), ("waves", ctypes.c_uint64),
-                ("waves_divergent", ctypes.c_uint64), ("status", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("waves_divergent", ctypes.c_uint64), ("off_mode", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 class Launch(ctypes.Structure):
@@ -57,7 +58,7 @@ EXPORTS = [
     "adept_autotune_type_layouts",
     "adept_stats_get", "adept_dump_tracks", "adept_dump_ring", "adept_reset", "adept_autotune",
     "adept_set_timing", "adept_autotune_layout", "adept_last_error", "adept_destroy", "adept_phase_clocks",
-    "adept_dump_tracks_noalloc",
+    "adept_dump_tracks_noalloc", "adept_set_divergence_count",
 ]
 
 _lib = None
@@ -101,6 +102,7 @@ def lib():
         "adept_reset": (i32, [P]),
         "adept_autotune": (i32, [P, P, u64, P]),
         "adept_set_timing": (i32, [P, i32]),
+        "adept_set_divergence_count": (i32, [P, i32]),
         "adept_phase_clocks": (i32, [P, P]),
         "adept_autotune_layout": (i32, [i32, u64, P, u32, u32, P, P, u64, P, P, P]),
         "adept_last_error": (ctypes.c_char_p, [P]),
@@ -271,7 +273,7 @@ def adept_stats_get(ctx):
             "counts": list(s.counts), "error_iter": s.error_iter, "survivors": list(s.survivors),
             "outputs": list(s.outputs), "step_kernel_ms": s.step_kernel_ms, "step_launches": s.step_launches,
             "waves": s.waves,
-            "waves_divergent": s.waves_divergent, "status": s.status}
+            "waves_divergent": s.waves_divergent, "off_mode": s.off_mode, "status": s.status}
 
 
 def adept_dump_tracks(ctx, ptype):
@@ -319,6 +321,10 @@ def adept_phase_clocks(ctx):
     out = np.zeros(8, dtype=np.uint64)
     _check(ctx, lib().adept_phase_clocks(ctx, out.ctypes.data_as(ctypes.c_void_p)), "adept_phase_clocks")
     return out
+
+
+def adept_set_divergence_count(ctx, on):
+    _check(ctx, lib().adept_set_divergence_count(ctx, int(on)), "adept_set_divergence_count")
 
 
 def adept_set_timing(ctx, on):

@@ -334,6 +334,7 @@ struct adept_ctx {
   unsigned fold_chunks = 1;
   // per-launch timing of the step kernel (adept_set_timing)
   int timing = 0;
+  int off_mode_on = 1;  // lane-weighted divergence count (adept_set_divergence_count)
   std::vector<hipEvent_t> ev;
   double step_ms = 0.0;
   unsigned long long step_launches = 0;
@@ -487,6 +488,7 @@ void fill_args(adept_ctx* c) {
   for (int d = 0; d < 3; ++d) a.kappa[d] = c->kappa[d];
   a.hold = c->hold;
   a.count_empty = 1;
+  a.off_mode_on = c->off_mode_on;
   c->scratch = (double*)(A + P.scratch);
   c->fold = (double*)(A + P.fold);
   c->fold_chunks = (unsigned)P.fold_chunks;
@@ -1182,6 +1184,7 @@ adept_status adept_stats_get(adept_ctx* c, adept_stats* out) {
   out->error_iter = h.error_iter;
   out->waves = h.waves;
   out->waves_divergent = h.waves_div;
+  out->off_mode = h.off_mode;
   out->status = h.error;
   return ADEPT_OK;
 }
@@ -1302,6 +1305,7 @@ adept_status adept_autotune(adept_ctx* c, const adept_primary* p, uint64_t n, ad
   for (uint32_t w = 0; w < 2; ++w)  // compaction tile: the block, then the wavefront
   for (uint32_t b : blocks)
     for (uint32_t k : ks) {
+      if (w && b != (uint32_t)kMaxBlock) continue;  // wavefront tiles: only the full block (two tracks per lane)
       adept_launch l{b, 0, k, w};
       adept_set_launch(c, &l);
       float ms = 0.f;
@@ -1443,6 +1447,14 @@ adept_status adept_phase_clocks(adept_ctx* c, uint64_t out[8]) {
   HIPCHK(hipMemcpy(&h, c->args.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
   static_assert(kPhases == 8, "adept_phase_clocks reports eight phases");
   for (int i = 0; i < kPhases; ++i) out[i] = h.phase[i];
+  return ADEPT_OK;
+}
+
+adept_status adept_set_divergence_count(adept_ctx* c, int on) {
+  if (!c) return ADEPT_E_INVALID;
+  c->off_mode_on = on ? 1 : 0;
+  c->args.off_mode_on = c->off_mode_on;
+  c->graph_valid = false;
   return ADEPT_OK;
 }
 

@@ -68,6 +68,7 @@ struct Ctrl {
   unsigned long long error_iter;
   unsigned long long steps[3], peak[3];
   unsigned long long waves, waves_div;
+  unsigned long long off_mode;      // track-steps whose outcome differs from their wavefront's most common
   unsigned long long surv[3];       // surviving source tracks per type (all iterations)
   unsigned long long outputs[3];    // tracks written into next buffers per type
   unsigned long long inj_ticket[2], inj_ntiles[2], inj_tot[3];
@@ -143,7 +144,7 @@ struct KArgs {
   unsigned long long hold;
   // epilogue behaviour: 1 = an iteration with nothing active still counts
   int count_empty;
-  int pad2;
+  int off_mode_on;             // count Ctrl::off_mode (the lane-weighted divergence diagnostic)
 };
 
 __device__ __forceinline__ unsigned long long ld_agent(const unsigned long long* p) {
@@ -393,7 +394,7 @@ struct TallyLDS {
 
 // Per-block statistics, flushed with one atomic per counter at the end.
 struct StatLDS {
-  unsigned long long waves, waves_div, surv[3];
+  unsigned long long waves, waves_div, off_mode, surv[3];
 };
 
 // Batched runs (several events) and cell scoring: deposits go through a
@@ -545,6 +546,39 @@ __device__ __forceinline__ void tally_init(TallyLDS& tl) {
     tl.cut[i] = 0.0;
   }
   if (threadIdx.x == 0) tl.esc = tl.rnd = 0.0;
+}
+
+// Divergence diagnostics of one wavefront step (outcome code = survived? | buffered
+// creations << 1, at most 7): whether any lanes disagree, and how many lanes
+// differ from the wavefront's most common outcome; also the survivor count.
+__device__ __forceinline__ void div_stats(StatLDS& ss, int D, bool valid, bool surv, int code, bool off_on) {
+  const unsigned long long vm = __ballot(valid);
+  if (!vm) return;
+  const int lane = __lane_id();
+  const int first = __ffsll((long long)vm) - 1;
+  const int ref = __builtin_amdgcn_readlane(code, first);
+  const unsigned long long dm = __ballot(valid && code != ref);
+  const unsigned long long sm = __ballot(valid && surv);
+  int most = 0;
+  if (dm && off_on) {  // lane masks of the eight codes from the three bit planes (scalar work)
+    const unsigned long long b0 = __ballot(code & 1), b1 = __ballot(code & 2), b2 = __ballot(code & 4);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const unsigned long long m = vm & ((k & 1) ? b0 : ~b0) & ((k & 2) ? b1 : ~b1) & ((k & 4) ? b2 : ~b2);
+      const int c = __popcll(m);
+      most = c > most ? c : most;
+    }
+  } else {
+    most = __popcll(vm);
+  }
+  if (lane == first) {
+    atomicAdd(&ss.waves, 1ull);
+    if (dm) {
+      atomicAdd(&ss.waves_div, 1ull);
+      if (off_on) atomicAdd(&ss.off_mode, (unsigned long long)(__popcll(vm) - most));
+    }
+    if (sm) atomicAdd(&ss.surv[D], (unsigned long long)__popcll(sm));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -747,7 +781,7 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
   if (blockIdx.x >= total) return;
   if (lds_tally) tally_init(tl);
   else cache_init(tc);
-  if (threadIdx.x == 0) ss.waves = ss.waves_div = ss.surv[0] = ss.surv[1] = ss.surv[2] = 0;
+  if (threadIdx.x == 0) ss.waves = ss.waves_div = ss.off_mode = ss.surv[0] = ss.surv[1] = ss.surv[2] = 0;
   if (ADEPT_PHASE_CLOCKS && threadIdx.x < kPhases) ph_acc[threadIdx.x] = 0;
   __syncthreads();
   const int lane = __lane_id();
@@ -794,20 +828,7 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
         lim_code = (surv ? 1 : 0) | (cr.n << 1);
         book(a, lds_tally ? &tl : nullptr, lds_tally ? nullptr : &tc, t.event, v0, dep, t.pos);
       }
-      {  // divergence diagnostic: lanes of a wavefront that disagree on the outcome
-        const unsigned long long vm = __ballot(valid);
-        if (vm) {
-          const int first = __ffsll((long long)vm) - 1;
-          const int ref = __builtin_amdgcn_readlane(lim_code, first);
-          const unsigned long long dm = __ballot(valid && lim_code != ref);
-          const unsigned long long sm = __ballot(valid && surv);
-          if (lane == first) {
-            atomicAdd(&ss.waves, 1ull);
-            if (dm) atomicAdd(&ss.waves_div, 1ull);
-            if (sm) atomicAdd(&ss.surv[D], (unsigned long long)__popcll(sm));
-          }
-        }
-      }
+      div_stats(ss, D, valid, surv, lim_code, a.off_mode_on != 0);
       // output counts of this track (constant indices only: the arrays stay in registers)
       if (valid) {
 #pragma unroll
@@ -954,6 +975,7 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
   if (threadIdx.x == 0) {
     atomicAdd(&c->waves, ss.waves);
     if (ss.waves_div) atomicAdd(&c->waves_div, ss.waves_div);
+    if (ss.off_mode) atomicAdd(&c->off_mode, ss.off_mode);
     for (int d = 0; d < 3; ++d)
       if (ss.surv[d]) atomicAdd(&c->surv[d], ss.surv[d]);
   }
@@ -1190,7 +1212,7 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step_wave(const KArgs a)
   if ((unsigned long long)blockIdx.x * (T / 64) >= total) return;
   if (lds_tally) tally_init(tl);
   else cache_init(tc);
-  if (threadIdx.x == 0) ss.waves = ss.waves_div = ss.surv[0] = ss.surv[1] = ss.surv[2] = 0;
+  if (threadIdx.x == 0) ss.waves = ss.waves_div = ss.off_mode = ss.surv[0] = ss.surv[1] = ss.surv[2] = 0;
   tickets_init(wt);
   if (ADEPT_PHASE_CLOCKS && threadIdx.x < kPhases) ph_acc[threadIdx.x] = 0;
   __syncthreads();
@@ -1231,20 +1253,7 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step_wave(const KArgs a)
         lim_code = (surv ? 1 : 0) | (cr.n << 1);
         book(a, lds_tally ? &tl : nullptr, lds_tally ? nullptr : &tc, t.event, v0, dep, t.pos);
       }
-      {  // divergence diagnostic: lanes of a wavefront that disagree on the outcome
-        const unsigned long long vm = __ballot(valid);
-        if (vm) {
-          const int first = __ffsll((long long)vm) - 1;
-          const int ref = __builtin_amdgcn_readlane(lim_code, first);
-          const unsigned long long dm = __ballot(valid && lim_code != ref);
-          const unsigned long long sm = __ballot(valid && surv);
-          if (lane == first) {
-            atomicAdd(&ss.waves, 1ull);
-            if (dm) atomicAdd(&ss.waves_div, 1ull);
-            if (sm) atomicAdd(&ss.surv[D], (unsigned long long)__popcll(sm));
-          }
-        }
-      }
+      div_stats(ss, D, valid, surv, lim_code, a.off_mode_on != 0);
       if (valid) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
@@ -1346,6 +1355,7 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step_wave(const KArgs a)
   if (threadIdx.x == 0) {
     atomicAdd(&c->waves, ss.waves);
     if (ss.waves_div) atomicAdd(&c->waves_div, ss.waves_div);
+    if (ss.off_mode) atomicAdd(&c->off_mode, ss.off_mode);
     for (int d = 0; d < 3; ++d)
       if (ss.surv[d]) atomicAdd(&c->surv[d], ss.surv[d]);
   }

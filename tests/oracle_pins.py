@@ -193,3 +193,26 @@ def ledger_mixed_shower(L, precision, scheme=oracle.DENSE, every_iteration=True)
     for t in range(3):  # a source step either survives (and is written again) or ends the track
         assert g["survivors"][t] <= st["track_steps"][t] and g["survivors"][t] <= g["outputs"][t]
     return o, g, st
+
+
+def divergence_groups(L, scheme=oracle.DENSE):
+    """The lane-weighted divergence count after one iteration of 100 positrons at
+    the front face along +z: the first 40 and the ten at 64..73 have 1.01 MeV
+    (range 0.80 mm, inside the first absorber: killed, two annihilation photons
+    buffered), the rest 10 MeV with a forced interaction length of 100 X0 (a 2.3
+    mm geometry step: survive, nothing created).  Group 0 holds 40 of the first
+    kind and 24 of the second (24 differ from the group's most common outcome),
+    group 1 ten and 26 (10 differ): 34.  Groups of 128 would give 50, of 32 give
+    18; counting the most common outcome itself would give 66."""
+    p = workloads.primaries(100, workloads.POSITRON, 10.0, num_ia_left=100.0)
+    short = list(range(40)) + list(range(64, 74))
+    p["E"][short] = 1.01
+    p["numIALeft"][short] = -1.0
+    o = oracle.Oracle(scheme, oracle.FP64, 1 << 10, [1], L=L)
+    assert o.inject(p) == 0
+    rc, nxt = o.step()
+    assert rc == 0
+    led = o.ledger()
+    o.close()
+    assert led["survivors"][1] == 50 and list(nxt) == [0, 50, 100], (led["survivors"], nxt)
+    assert led["off_mode"] == 34, led["off_mode"]

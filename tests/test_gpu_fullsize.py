@@ -92,6 +92,7 @@ def compare_step_counters(st0, st1, o):
                       ("outputs", led["outputs"])):
         got = [b - a for a, b in zip(st0[key], st1[key])]
         assert got == list(want), (key, got, list(want))
+    assert st1["off_mode"] - st0["off_mode"] == led["off_mode"]
 
 
 FULL_CASES = [  # precision, scheme, mapping, lanes, block, wave tiles

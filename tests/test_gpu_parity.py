@@ -104,6 +104,7 @@ def test_iterations_bitwise(ad, oracle_mod, scheme, mapping, lanes, precision, b
     assert gs["track_steps"] == ws["track_steps"] and gs["iterations"] == ws["iterations"]
     led = o.ledger()  # the counters the roofline's byte count is built from
     assert gs["survivors"] == led["survivors"] and gs["outputs"] == led["outputs"], (gs, led)
+    assert gs["off_mode"] == led["off_mode"], (gs["off_mode"], led["off_mode"])  # divergence diagnostic
     sim.close()
 
 
@@ -127,6 +128,7 @@ def test_anchor_run_graph(ad, oracle_mod, block, wave):
     assert gs["track_steps"] == ws["track_steps"] and gs["peak"] == ws["peak"]
     led = o.ledger()
     assert gs["survivors"] == led["survivors"] and gs["outputs"] == led["outputs"]
+    assert gs["off_mode"] == led["off_mode"]
     compare_tallies(sim, o, oracle_mod)
     for t in range(3):
         gr, gh, gc = sim.ring(t)

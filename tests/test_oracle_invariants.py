@@ -345,3 +345,24 @@ def test_admission_reservation_limits(oracle_mod):
     assert np.allclose(inf.tally(oracle_mod.T_LAYER), zero.tally(oracle_mod.T_LAYER), rtol=1e-12, atol=1e-12)
     assert inf.stats()["track_steps"] == zero.stats()["track_steps"]
     assert len(trace_inf) > len(trace_zero)
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_divergence_diagnostic_groups_of_64(oracle_mod, scheme):
+    """Per group of 64 consecutive sources of a type, the sources whose outcome
+    differs from the group's most common one (case and expected count in
+    oracle_pins.divergence_groups)."""
+    import oracle_pins
+
+    oracle_pins.divergence_groups(oracle_mod.load(oracle_mod.LIB), scheme)
+
+
+def test_divergence_diagnostic_zero_for_uniform_groups(oracle_mod):
+    """Identical photons that never interact share every outcome: nothing differs."""
+    p = workloads.primaries(130, workloads.GAMMA, 10.0, num_ia_left=1000.0)
+    o = oracle_mod.Oracle(1, oracle_mod.FP64, 1 << 10, [1])
+    assert o.inject(p) == 0
+    for _ in range(5):
+        assert o.step()[0] == 0
+    assert o.ledger()["off_mode"] == 0
+    o.close()

@@ -41,6 +41,12 @@ MUTATIONS = [
      "create(S, &X, OR_POSITRON, Tp, t->pos, t->dir, v1, out);\n    return 0;\n  }\n  double Enew",
      "create(S, &X, OR_ELECTRON, Tp, t->pos, t->dir, v1, out);\n    return 0;\n  }\n  double Enew",
      [lambda L: pins.ledger_mixed_shower(L, FP64)]),
+    ("divergence groups of 128 sources",
+     "if ((i & 63) == 63 || i + 1 == S->n[D]) {", "if ((i & 127) == 127 || i + 1 == S->n[D]) {",
+     [lambda L: pins.divergence_groups(L)]),
+    ("divergence count includes the most common outcome",
+     "S->led.off_mode += all - most;", "S->led.off_mode += all;",
+     [lambda L: pins.divergence_groups(L)]),
 ]
 
 
