@@ -23,6 +23,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, AMD's published figure
 KERNEL_SOURCES = ["kernels.hpp", "layout.hpp", "model.hpp", "inst_dense_mixed.hip"]
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_step_100ke_10gev_dense_soa_mixed_pmc.md")
+BATCHED_TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_step_512_uneven_events_dense_aosoa64_mixed_pmc.md")
 
 
 def progress(msg):
@@ -40,11 +41,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def profile_fields():
-    """The '- key: value' lines of the committed rocprofv3 --pmc summary of the
-    headline kernel, or {} if the kernel sources changed since it was taken."""
+def profile_fields(path=TRAFFIC_SUMMARY):
+    """The '- key: value' lines of a committed rocprofv3 --pmc summary (by default the
+    headline kernel's), or {} if the kernel sources changed since it was taken."""
     try:
-        text = open(TRAFFIC_SUMMARY).read()
+        text = open(path).read()
     except OSError:
         return {}
     fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith("- ") and ":" in line)
@@ -52,11 +53,11 @@ def profile_fields():
     return fields if fields.get("kernel source hash") == kernel_source_hash() else {}
 
 
-def measured_traffic():
+def measured_traffic(path=TRAFFIC_SUMMARY):
     """HBM bytes per step-kernel launch (FETCH_SIZE + WRITE_SIZE, scaled by the same
     counters on a plain copy of known size), or None."""
     try:
-        return float(profile_fields()["scaled HBM bytes per launch"])
+        return float(profile_fields(path)["scaled HBM bytes per launch"])
     except (KeyError, ValueError):
         return None
 
@@ -338,6 +339,9 @@ def batched_section(ad, torch, np, workloads, args):
                     "divergent_wave_fraction": st["waves_divergent"] / max(st["waves"], 1),
                     "lanes_off_mode_fraction": st_w["off_mode"] / max(sum(st_w["track_steps"]), 1),
                     "roofline": kernel_roofline(st_t, layout[0], 1)}
+    # the layout and tile shape the counter summary was taken with
+    if layout == (1, 2, 64) and launch.get("block") == 1024 and not launch.get("wave_tiles"):
+        out["mixed"]["roofline"]["traffic"] = measured_traffic(BATCHED_TRAFFIC_SUMMARY)
     # the FP64 sparse single buffer (the paper's baseline structure), same admission
     sp = ad.Sim(0, 0, ad.FP64, C, 1, seeds=wl.seeds, admission=(0.8, kappa), launch=launch)
     dt2, it2, st2 = run_once(ad, torch, sp, wl.primaries)
