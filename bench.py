@@ -91,6 +91,8 @@ def parse():
                     help="only the 512 uneven events, twice, with the tuned layout fixed (AoSoA-64, block 1024, "
                          "graphs of 16): the command behind the batched kernel-trace summary")
     ap.add_argument("--per-event-sample", type=int, default=32, help="events timed one launch sequence each")
+    ap.add_argument("--batched-capacity-log2", type=int, default=28,
+                    help="slots per particle type of the 512-event runs (admission keeps the tracks below 0.8 of it)")
     ap.add_argument("--no-segmented", action="store_true", help="skip 10^6 e- in 1000 events with 500k cells")
     ap.add_argument("--no-layout-study", action="store_true",
                     help="skip showers_10ke_10gev in the paper's four layouts (timings and access counts)")
@@ -307,10 +309,13 @@ def run_once(ad, torch, sim, prims=None, dev=None):
 
 def batched_section(ad, torch, np, workloads, args):
     """512 uneven events (uneven_512_events): layout and launch picked by the autotuner on a
-    64-event sample, events admitted by the capacity rule, per-event tallies."""
+    64-event sample, events admitted by the capacity rule, per-event tallies.  The track
+    buffers get most of the HBM (2^28 slots per type by default, 122 GB in the mixed
+    record): admission then takes every event at once and the run needs 251 iterations
+    instead of 1937 at 2^24, with fewer, larger launches."""
     wl = workloads.uneven_512_events()
     kappa = kappa_per_gev()
-    C = 1 << 24
+    C = 1 << args.batched_capacity_log2
     cands = [(1, 0, 1), (1, 1, 1), (1, 2, 16), (1, 2, 64), (1, 2, 256)]
     sample = wl.primaries[wl.primaries["event"] < 64]  # ~64k primaries: peak below 1e7 photons < 2^24
     layout, launch, _ = ad.adept_autotune_layout(ad.MIXED, 1 << 24, cands, wl.seeds[:64], sample)
@@ -339,8 +344,9 @@ def batched_section(ad, torch, np, workloads, args):
                     "divergent_wave_fraction": st["waves_divergent"] / max(st["waves"], 1),
                     "lanes_off_mode_fraction": st_w["off_mode"] / max(sum(st_w["track_steps"]), 1),
                     "roofline": kernel_roofline(st_t, layout[0], 1)}
-    # the layout and tile shape the counter summary was taken with
-    if layout == (1, 2, 64) and launch.get("block") == 1024 and not launch.get("wave_tiles"):
+    # the layout, tile shape and capacity the counter summary was taken with
+    if (layout == (1, 2, 64) and launch.get("block") == 1024 and not launch.get("wave_tiles")
+            and profile_fields(BATCHED_TRAFFIC_SUMMARY).get("capacity per type") == str(C)):
         out["mixed"]["roofline"]["traffic"] = measured_traffic(BATCHED_TRAFFIC_SUMMARY)
     # the FP64 sparse single buffer (the paper's baseline structure), same admission
     sp = ad.Sim(0, 0, ad.FP64, C, 1, seeds=wl.seeds, admission=(0.8, kappa), launch=launch)
@@ -371,9 +377,9 @@ def batched_section(ad, torch, np, workloads, args):
     return out
 
 
-def batched_profile(ad, torch, np, workloads):
+def batched_profile(ad, torch, np, workloads, args):
     wl = workloads.uneven_512_events()
-    sim = ad.Sim(ad.DENSE_DOUBLE, ad.MAP_AOSOA, ad.MIXED, 1 << 24, 64, seeds=wl.seeds,
+    sim = ad.Sim(ad.DENSE_DOUBLE, ad.MAP_AOSOA, ad.MIXED, 1 << args.batched_capacity_log2, 64, seeds=wl.seeds,
                  admission=(0.8, kappa_per_gev()), launch={"block": 1024, "graph_iters": 16})
     runs = []
     for _ in range(2):
@@ -600,7 +606,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if args.batched_profile:
-        print(json.dumps({"batched_profile": batched_profile(ad, torch, np, workloads)}), flush=True)
+        print(json.dumps({"batched_profile": batched_profile(ad, torch, np, workloads, args)}), flush=True)
         return
     if args.line_check:
         print(json.dumps({"line_check": line_check(ad, torch, np, workloads, args.line_check)}), flush=True)

@@ -412,6 +412,7 @@ class Sim:
         if getattr(self, "ctx", None):
             adept_destroy(self.ctx)
             self.ctx = None
+        self.arena = None  # the device arena goes back to torch's allocator
 
     def __del__(self):
         try:

@@ -12,7 +12,9 @@
   1024-lane tiles, admission, 2^24 slots), with and without 100x100 cells per layer,
   handed over right after its last event is admitted (the later events' showers
   then near their peak): next state bitwise, per-event and per-cell deposits of
-  the iteration within 1e-12.
+  the iteration within 1e-12.  The same workload with the capacity the benchmark
+  gives it (2^28 slots per type) handed over at iteration 80 (83 million active
+  tracks, record addresses beyond 4 GiB).
 * The mixed-precision criterion: 4000 primaries of the headline workload in mixed
   precision on the GPU against the FP64 oracle: per-layer deposits within 1e-4 on
   every layer holding at least 1e-3 of the total; the number of showers in which
@@ -174,6 +176,67 @@ def test_batched_handover_after_last_admission(ad, oracle_mod, cells, wave):
     rc, w = o.step()
     assert rc == 0 and list(g) == list(w)
     compare_next_state(sim, o, 1, "batched")
+    compare_step_counters(st0, sim.stats(), o)
+    for k, b in before.items():
+        after = sim.tally(k)
+        inc, want = after - b, o.tally(k)
+        assert np.all(np.abs(inc - want) <= 1e-12 * np.abs(after).max() + 1e-9), k
+    sim.close()
+    o.close()
+
+
+def compare_next_state_chunked(sim, o, what, chunk=1 << 22):
+    """compare_next_state for the dense scheme without whole-array byte copies."""
+    for t in range(3):
+        g, _ = sim.dump(t)
+        w, _ = o.dump(t)
+        assert len(g) == len(w), (what, t, len(g), len(w))
+        for i in range(0, len(g), chunk):
+            a, b = g[i:i + chunk], w[i:i + chunk]
+            if a.tobytes() != b.tobytes():
+                diff = np.nonzero((a.view(np.uint8).reshape(len(a), -1) != b.view(np.uint8).reshape(len(b), -1))
+                                  .any(axis=1))[0]
+                raise AssertionError(f"{what} type {t}: tracks differ from {i + diff[0]}: gpu {a[diff[0]]} "
+                                     f"oracle {b[diff[0]]}")
+        del g, w
+
+
+def test_batched_handover_at_hbm_capacity(ad, oracle_mod):
+    """The 512-event workload with the capacity the benchmark gives it (2^28 slots per
+    type, 122 GB of track buffers in AoSoA-64: every event is admitted in the first
+    iteration), handed over at iteration 80, when more than 2^32 / 76 photons are
+    active, so that record addresses pass 4 GiB: next state bitwise, the iteration's
+    counters equal and its per-event deposits within 1e-12."""
+    import psutil
+    import torch
+
+    C = 1 << 28
+    free, _ = torch.cuda.mem_get_info()
+    if free < 140e9:
+        pytest.skip(f"needs 140 GB of free device memory, {free / 1e9:.0f} GB free")
+    if psutil.virtual_memory().available < 80e9:
+        pytest.skip("needs 80 GB of free host memory for the oracle's copy of the state")
+    say("case batched handover at 2^28 slots per type, iteration 80")
+    wl = workloads.uneven_512_events()
+    sim = ad.Sim(1, 2, 1, C, 64, seeds=wl.seeds, admission=(0.8, kappa()),
+                 launch={"block": 1024, "graph_iters": 16})
+    sim.inject(wl.primaries)
+    it = 80
+    assert sim.run(it) == it
+    assert np.all(sim.tally(oracle_mod.T_EIN) > 0)
+    o = oracle_mod.Oracle(1, 1, C, wl.seeds)
+    n_active = hand_over(sim, o, 1, it)
+    say(f"  {n_active} active tracks handed over")
+    n_gamma = int(sim.counts()[2])
+    assert n_gamma * 76 > 1 << 32, n_gamma
+    kinds = [oracle_mod.T_DEP_CONT, oracle_mod.T_DEP_CUT, oracle_mod.T_ESCAPED, oracle_mod.T_ROUND]
+    before = {k: sim.tally(k) for k in kinds}
+    st0 = sim.stats()
+    g = sim.step()
+    rc, w = o.step()
+    say(f"  one iteration stepped on both sides: {list(g)}")
+    assert rc == 0 and list(g) == list(w)
+    compare_next_state_chunked(sim, o, "batched, 2^28 slots")
     compare_step_counters(st0, sim.stats(), o)
     for k, b in before.items():
         after = sim.tally(k)
