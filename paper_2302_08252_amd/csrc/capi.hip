@@ -378,19 +378,16 @@ uint64_t buf_bytes_of(const adept_ctx* c, int t) {
   return c->prec ? buffer_bytes<true>(l.mapping, l.aosoa_lanes, c->C) : buffer_bytes<false>(l.mapping, l.aosoa_lanes, c->C);
 }
 
-// Tally rows: the flat tally index space of one block (202 per event, then the
-// cells).  A single event without cells keeps one row for every possible block;
-// otherwise up to kBatchRows rows cover the grid of 1024-lane blocks (2 per CU),
-// fewer if they would pass kRowBytes, and a block beyond them adds to the
-// tallies directly (correct, with device-scope atomics).
-constexpr size_t kBatchRows = 512;
-constexpr size_t kRowBytes = size_t(4) << 30;
+// Tally rows: the flat tally index space (202 per event, then the cells).  A
+// single event without cells keeps one row for every possible block (written by
+// that block alone when its launch ends); otherwise the blocks' LDS caches spill
+// into the row of their XCD, one for each of the kXccRows hardware XCC ids.
 size_t row_len_of(const adept_ctx* c) {
   return (size_t)kRowLen * c->seeds.size() + (size_t)kNumLayer * c->nx * c->ny;
 }
 size_t rows_of(const adept_ctx* c) {
   if (c->seeds.size() == 1 && c->nx * c->ny == 0) return (size_t)kMaxGrid;
-  return std::max<size_t>(1, std::min(kBatchRows, kRowBytes / (row_len_of(c) * 8)));
+  return (size_t)kXccRows;
 }
 
 Plan plan(const adept_ctx* c) {

@@ -55,6 +55,7 @@ constexpr int kMaxBlock = 1024;
 constexpr int kMaxWaves = kMaxBlock / 64;
 constexpr unsigned kMaxGrid = 8192;          // largest grid of the step kernel
 constexpr int kRowLen = 2 * 100 + 2;         // continuous[100], local[100], escaped, rounding
+constexpr unsigned kXccRows = 16;            // tally rows per XCD id (the hardware XCC id has 4 bits)
 
 // Device control block (one per context, in the arena).  Index p = parity
 // selects the current iteration's counts / lists / dense buffers.
@@ -115,10 +116,11 @@ struct KArgs {
   double* rnd;                 // [event]
   double* ein;                 // [event]
   double* cells;               // [50][nx][ny] or null
-  double* rows;                // one tally row per block index (row_len doubles, n_rows rows): partial sums
-                               // of the block's deposits, folded into the tallies when they are read
+  double* rows;                // tally rows (row_len doubles each, n_rows rows): partial sums folded into
+                               // the tallies when they are read.  A single event without cells: one row per
+                               // block index; otherwise one row per XCD (hardware XCC id)
   unsigned long long row_len;  // 202 * events + cells: the flat tally index space
-  unsigned n_rows;             // blocks at or beyond this index add to the tallies directly
+  unsigned n_rows;             // rows allocated (per block index, or kXccRows)
   unsigned pad_rows;
   uint32_t nx, ny;
   double pitch;
@@ -420,15 +422,20 @@ __device__ __forceinline__ double* tally_ptr(const KArgs& a, uint32_t key) {
   return a.cells + (key - 202u * E);
 }
 
-// Where a block's deposits go past its LDS cache: its own row while the launch
-// runs (only this block writes it, so the atomic need not leave the XCD), or
-// the tallies themselves for a block beyond the allocated rows.
+// The XCD (accelerator complex die, one L2 cache) the calling workgroup runs on.
+__device__ __forceinline__ uint32_t xcc_id() {
+  uint32_t x;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(x));
+  return x;
+}
+
+// Where a block's deposits go past its LDS cache: the row of its XCD.  Every
+// block that adds to a row runs on that row's XCD, so the row's lines stay in
+// one L2 (827 KB for 512 events, against 4 MB of L2 per XCD), where the atomics
+// are performed; the rows reach memory when the launch ends.
 __device__ __forceinline__ void spill_add(const KArgs& a, uint32_t key, double v) {
-  if (blockIdx.x < a.n_rows)
-    __hip_atomic_fetch_add(a.rows + (unsigned long long)blockIdx.x * a.row_len + key, v, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_WORKGROUP);
-  else
-    __hip_atomic_fetch_add(tally_ptr(a, key), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_fetch_add(a.rows + (unsigned long long)xcc_id() * a.row_len + key, v, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <class TC>
