@@ -102,6 +102,8 @@ def parse():
                     help="showers_10ke_10gev, FP64: injection + 20 iterations uninstrumented (the dispatches a "
                          "counter run measures), then the same instrumented, printing the cache-line model of "
                          "the bytes moved")
+    ap.add_argument("--layout-pair", action="store_true",
+                    help="the headline workload once in SoA and once in AoSoA-64 (graph replay), for counter runs")
     ap.add_argument("--pmc-summary", nargs="+", default=None, metavar="CSV",
                     help="sum rocprofv3 counter CSVs per kernel and counter (no GPU use)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -428,6 +430,22 @@ def line_check(ad, torch, np, workloads, which):
             "algorithmic_step_bytes": algorithmic_bytes(st, s, 0)}
 
 
+def layout_pair(ad, torch, wl, args):
+    """The headline workload (mixed, dense) once in SoA and once in AoSoA-64, graph
+    replay, for counter runs that compare the two layouts (k_step<1, 1, ...> is the
+    SoA kernel, k_step<1, 2, ...> the AoSoA one)."""
+    out = []
+    for mapping, lanes, name in ((ad.MAP_SOA, 1, "SoA"), (ad.MAP_AOSOA, 64, "AoSoA-64")):
+        sim = ad.Sim(ad.DENSE_DOUBLE, mapping, ad.MIXED, 1 << args.capacity_log2, lanes, seeds=wl.seeds,
+                     launch={"block": args.block, "graph_iters": args.graph_iters})
+        ad.adept_set_divergence_count(sim.ctx, False)
+        dt, it, st = run_once(ad, torch, sim, wl.primaries)
+        out.append({"layout": name, "seconds": dt, "iterations": it, "track_steps_per_s": sum(st["track_steps"]) / dt})
+        sim.close()
+        del sim
+    return out
+
+
 def kernel_base_name(name):
     """A kernel's name without its trailing argument list."""
     if name.endswith(")"):
@@ -610,6 +628,9 @@ def main():
         return
     if args.line_check:
         print(json.dumps({"line_check": line_check(ad, torch, np, workloads, args.line_check)}), flush=True)
+        return
+    if args.layout_pair:
+        print(json.dumps({"layout_pair": layout_pair(ad, torch, wl, args)}), flush=True)
         return
     C = 1 << args.capacity_log2
     dev_prims = torch.from_numpy(wl.primaries.view(np.uint8).copy()).cuda()
