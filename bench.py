@@ -317,7 +317,15 @@ def batched_section(ad, torch, np, workloads, args):
     instead of 1937 at 2^24, with fewer, larger launches."""
     wl = workloads.uneven_512_events()
     kappa = kappa_per_gev()
-    C = 1 << args.batched_capacity_log2
+    # the largest capacity up to the requested one whose mixed AoSoA-64 buffers (six
+    # of 76 bytes per slot) fit in 90 % of the free device memory
+    free, _ = torch.cuda.mem_get_info()
+    lg = args.batched_capacity_log2
+    while lg > 20 and 6 * 76 * (1 << lg) > 0.9 * free:
+        lg -= 1
+    C = 1 << lg
+    if lg != args.batched_capacity_log2:
+        progress(f"batched: 2^{args.batched_capacity_log2} slots per type do not fit, using 2^{lg}")
     cands = [(1, 0, 1), (1, 1, 1), (1, 2, 16), (1, 2, 64), (1, 2, 256)]
     sample = wl.primaries[wl.primaries["event"] < 64]  # ~64k primaries: peak below 1e7 photons < 2^24
     layout, launch, _ = ad.adept_autotune_layout(ad.MIXED, 1 << 24, cands, wl.seeds[:64], sample)
