@@ -102,6 +102,8 @@ def parse():
                     help="showers_10ke_10gev, FP64: injection + 20 iterations uninstrumented (the dispatches a "
                          "counter run measures), then the same instrumented, printing the cache-line model of "
                          "the bytes moved")
+    ap.add_argument("--segmented-profile", action="store_true",
+                    help="only the 1000-event cell workload, mixed, twice (for profilers)")
     ap.add_argument("--layout-pair", action="store_true",
                     help="the headline workload once in SoA and once in AoSoA-64 (graph replay), for counter runs")
     ap.add_argument("--pmc-summary", nargs="+", default=None, metavar="CSV",
@@ -399,6 +401,22 @@ def batched_profile(ad, torch, np, workloads, args):
     return {"workload": wl.description, "layout": "dense AoSoA-64, mixed", "runs": runs}
 
 
+def segmented_profile(ad, torch, np, workloads):
+    """The mixed run of the segmented section, twice (graph replay), for counter runs."""
+    wl = workloads.segmented_1000_events()
+    sim = ad.Sim(ad.DENSE_DOUBLE, ad.MAP_SOA, ad.MIXED, 1 << 28, 64, seeds=wl.seeds, scoring=(100, 100, 4.0),
+                 admission=(0.8, kappa_per_gev()), launch={"block": 1024, "graph_iters": 32})
+    ad.adept_set_divergence_count(sim.ctx, False)
+    runs = []
+    for _ in range(2):
+        dt, it, st = run_once(ad, torch, sim, wl.primaries)
+        runs.append({"seconds": dt, "iterations": it, "track_steps_per_s": sum(st["track_steps"]) / dt,
+                     "algorithmic_bytes": algorithmic_bytes(st, 1, 1)})
+    sim.close()
+    return {"workload": wl.description + ", 100x100 cells of 4 mm per layer", "layout": "dense SoA, mixed",
+            "runs": runs}
+
+
 LINE_LAYOUTS = {"sparse-aos": (0, 0, 1), "dense-aos": (1, 0, 1), "dense-soa": (1, 1, 1)}
 
 
@@ -636,6 +654,9 @@ def main():
         return
     if args.line_check:
         print(json.dumps({"line_check": line_check(ad, torch, np, workloads, args.line_check)}), flush=True)
+        return
+    if args.segmented_profile:
+        print(json.dumps({"segmented_profile": segmented_profile(ad, torch, np, workloads)}), flush=True)
         return
     if args.layout_pair:
         print(json.dumps({"layout_pair": layout_pair(ad, torch, wl, args)}), flush=True)
