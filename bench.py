@@ -32,12 +32,15 @@ def progress(msg):
 
 
 def kernel_source_hash():
+    """Hash of the step kernel's sources and of the build script (its compiler flags)."""
     import hashlib
 
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2302_08252_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_2302_08252_amd", "build.py"), "rb") as fh:
+        h.update(fh.read())
     return h.hexdigest()[:16]
 
 

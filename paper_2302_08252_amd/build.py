@@ -18,9 +18,13 @@ ARCH = os.environ.get("ADEPT_OFFLOAD_ARCH", "gfx950")
 SOURCES = ["capi.hip", "inst_dense_f64.hip", "inst_dense_mixed.hip", "inst_sparse_f64.hip", "inst_sparse_mixed.hip",
            "inst_typed.hip"]
 HEADERS = ["kernels.hpp", "layout.hpp", "model.hpp", os.path.join("..", "..", "include", "adept.h")]
+# -amdgpu-sched-strategy=max-ilp: the backend's instruction scheduler set to maximise
+# instruction-level parallelism within a wavefront (measured: the step kernel 0.6 % faster on
+# 10^5 e- x 10 GeV, 0.9 % on the 512-event workload; the default and max-memory-clause tie)
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-munsafe-fp-atomics",
-    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-function",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-mllvm", "-amdgpu-sched-strategy=max-ilp",
+    "-Wall", "-Wno-unused-function",
 ]
 
 
