@@ -18,6 +18,15 @@
 
 #define AD_HD __host__ __device__ __forceinline__
 
+// Random-number blocks that several divergent paths of a step use are drawn once
+// per step, by every lane, before the paths split: a wavefront then runs the
+// Philox rounds once instead of once per path that any of its lanes takes.
+// ADEPT_RNG_PER_PATH=1 builds the form that draws them on each path (same
+// numbers, same results), to measure what the hoisting saves; 0 in normal builds.
+#ifndef ADEPT_RNG_PER_PATH
+#define ADEPT_RNG_PER_PATH 0
+#endif
+
 namespace adept {
 
 enum : int { ELECTRON = 0, POSITRON = 1, GAMMA = 2 };
@@ -495,11 +504,17 @@ AD_HD bool step_charged(Track<typename P::R>& t, int type, Creations<typename P:
   // Block 1 serves the interaction-length resample after a brem and the
   // annihilation direction; one of the two occurs in nearly every wavefront, so
   // it is drawn once here rather than on each path.
+#if !ADEPT_RNG_PER_PATH
   const U4 b = track_block<P::philox_unroll>(t.seed, t.id, n, 1u);
+#endif
   if (E1 < C::cut_e) {
     dep.cut += (double)E1;
     t.vol = v1;
+#if ADEPT_RNG_PER_PATH
+    if (type == POSITRON) annihilate<P>(track_block<P::philox_unroll>(t.seed, t.id, n, 1u), X, &kidx, 0, out);
+#else
     if (type == POSITRON) annihilate<P>(b, X, &kidx, 0, out);
+#endif
     return false;
   }
   const R th0 = (C::msc / E0) * F::sqrt_(sr_ / lam);
@@ -516,6 +531,9 @@ AD_HD bool step_charged(Track<typename P::R>& t, int type, Creations<typename P:
     const R E2 = E1 - k;
     k = E1 - E2;
     create<P>(X, &kidx, GAMMA, k, out, dep);
+#if ADEPT_RNG_PER_PATH
+    const U4 b = track_block<P::philox_unroll>(t.seed, t.id, n, 1u);
+#endif
     nl = -plog<R>(P::uni(b.x));
     E = E2;
     if (E2 < C::cut_e) {
@@ -546,8 +564,12 @@ AD_HD bool step_photon(Track<typename P::R>& t, Creations<typename P::R>& out, D
   // Block 0 gives the initial interaction length and the interaction's split.
   // Almost every wavefront holds a new photon and an interacting one, so the
   // block is drawn once for all lanes instead of on each of the two paths.
+#if ADEPT_RNG_PER_PATH
+  if (nl < (R)0) nl = -plog<R>(P::uni(track_block<P::philox_unroll>(t.seed, t.id, n, 0u).x));
+#else
   const U4 a = track_block<P::philox_unroll>(t.seed, t.id, n, 0u);
   if (nl < (R)0) nl = -plog<R>(P::uni(a.x));
+#endif
   const bool pair = E > C::pairth;
   const R lam = pair ? C::lpair(m) : C::lcomp(m);
   const R s_phys = nl * lam;
@@ -565,7 +587,12 @@ AD_HD bool step_photon(Track<typename P::R>& t, Creations<typename P::R>& out, D
     return false;
   }
   t.vol = v1;
+#if ADEPT_RNG_PER_PATH
+  uint32_t a3 = 0;
+  if (lim == LIM_PHYS) a3 = track_block<P::philox_unroll>(t.seed, t.id, n, 0u).w;
+#else
   const uint32_t a3 = a.w;
+#endif
   if (lim == LIM_PHYS && pair) {
     R T, r;
     two_sum<R>(E, -C::pairth, &T, &r);
