@@ -44,6 +44,18 @@ struct U4 {
   uint32_t x, y, z, w;
 };
 
+// Three-way XOR: one gfx950 v_bitop3_b32 (truth table 0x96, the parity of its
+// three inputs) where the compiler would issue two v_xor_b32.
+AD_HD uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+#else
+  return a ^ b ^ c;
+#endif
+}
+
 // U: rounds per loop iteration (a divisor of 10), a tuning choice of the
 // precision policy.  Fully unrolled, the round keys of each inlined call fold
 // into distinct constants that crowd the scalar registers; a short loop keeps
@@ -54,7 +66,7 @@ AD_HD U4 philox(U4 c, uint32_t k0, uint32_t k1) {
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
-    const U4 n = {(uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0};
+    const U4 n = {xor3((uint32_t)(p1 >> 32), c.y, k0), (uint32_t)p1, xor3((uint32_t)(p0 >> 32), c.w, k1), (uint32_t)p0};
     c = n;
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
