@@ -588,6 +588,17 @@ __device__ __forceinline__ void div_stats(StatLDS& ss, int D, bool valid, bool s
   }
 }
 
+// Creations of each particle type: the type fields of the three slots sit at bits
+// 8s and 8s + 1 of the metadata, and a slot not pushed reads as type 0, so type 0
+// is what remains of the count after types 1 and 2 (two bit planes, two popcounts).
+template <class R>
+__device__ __forceinline__ void creation_counts(const Creations<R>& cr, uint32_t c[3]) {
+  const uint32_t lo = cr.meta & 0x010101u, hi = (cr.meta >> 1) & 0x010101u;
+  c[1] = (uint32_t)__popc(lo & ~hi);
+  c[2] = (uint32_t)__popc(hi & ~lo);
+  c[0] = (uint32_t)cr.n - c[1] - c[2];
+}
+
 // ---------------------------------------------------------------------------
 // Track load / store through the accessor.
 // ---------------------------------------------------------------------------
@@ -838,11 +849,11 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
       div_stats(ss, D, valid, surv, lim_code, a.off_mode_on != 0);
       // output counts of this track (constant indices only: the arrays stay in registers)
       if (valid) {
+        uint32_t cc[3];
+        creation_counts(cr, cc);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          uint32_t c_new = 0;
-#pragma unroll
-          for (int i = 0; i < 3; ++i) c_new += (i < cr.n && cr.type(i) == d) ? 1u : 0u;
+          const uint32_t c_new = cc[d];
           cnt[u * NV + d] = c_new + ((surv && D == d) ? 1u : 0u);
           if (SCHEME == SPARSE) {
             cnt[u * NV + 3 + d] = c_new;
@@ -1262,11 +1273,11 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step_wave(const KArgs a)
       }
       div_stats(ss, D, valid, surv, lim_code, a.off_mode_on != 0);
       if (valid) {
+        uint32_t cc[3];
+        creation_counts(cr, cc);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          uint32_t c_new = 0;
-#pragma unroll
-          for (int i = 0; i < 3; ++i) c_new += (i < cr.n && cr.type(i) == d) ? 1u : 0u;
+          const uint32_t c_new = cc[d];
           cnt[u * NV + d] = c_new + ((surv && D == d) ? 1u : 0u);
           if (SCHEME == SPARSE) {
             cnt[u * NV + 3 + d] = c_new;
