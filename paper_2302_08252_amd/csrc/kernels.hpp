@@ -290,12 +290,16 @@ __device__ __forceinline__ void block_scan(const uint32_t cnt[NV], uint32_t lex[
   __syncthreads();
 #pragma unroll
   for (int w = 0; w < W; ++w) {
-    unsigned long long before = 0, all = 0;
-    for (int j = 0; j < nw; ++j) {
-      const unsigned long long t = widen3(sh.wave_tot[j][w]);
-      if (j < wave) before += t;
-      all += t;
-    }
+    // lane j < nw takes wave j's totals, widened to 16-bit fields (fields 0 and 1
+    // in one word, field 2 in another: sums stay below 2^13, so no carries cross
+    // fields); an inclusive scan over the first row of 16 lanes then holds every
+    // prefix of the wave totals, read out for this wavefront and for the block
+    const uint32_t tw = lane < nw ? sh.wave_tot[lane][w] : 0u;
+    const uint32_t lo = row_scan((tw & 0x3FFu) | ((tw & 0xFFC00u) << 6));
+    const uint32_t hi = row_scan((tw & 0x3FF00000u) >> 20);
+    const unsigned long long sc = ((unsigned long long)hi << 32) | lo;
+    const unsigned long long before = wave > 0 ? lane_value(sc, wave - 1) : 0ull;
+    const unsigned long long all = lane_value(sc, nw - 1);
     const unsigned long long ex = before + widen3(inc[w] - x[w]);
 #pragma unroll
     for (int k = 0; k < 3; ++k)
