@@ -562,6 +562,44 @@ __device__ __forceinline__ void tally_init(TallyLDS& tl) {
 // Divergence diagnostics of one wavefront step (outcome code = survived? | buffered
 // creations << 1, at most 7): whether any lanes disagree, and how many lanes
 // differ from the wavefront's most common outcome; also the survivor count.
+// Counts of one wavefront over the tracks it steps in a tile (wave-uniform
+// values, added to the block's LDS statistics once per tile).
+struct DivCount {
+  uint32_t waves, waves_div, off_mode, surv;
+};
+__device__ __forceinline__ void div_count(DivCount& k, bool valid, bool surv, int code, bool off_on) {
+  const unsigned long long vm = __ballot(valid);
+  if (!vm) return;
+  const int first = __ffsll((long long)vm) - 1;
+  const int ref = __builtin_amdgcn_readlane(code, first);
+  const unsigned long long dm = __ballot(valid && code != ref);
+  const unsigned long long sm = __ballot(valid && surv);
+  k.waves += 1u;
+  k.surv += (uint32_t)__popcll(sm);
+  if (dm) {
+    k.waves_div += 1u;
+    if (off_on) {  // lane masks of the eight codes from the three bit planes (scalar work)
+      const unsigned long long b0 = __ballot(code & 1), b1 = __ballot(code & 2), b2 = __ballot(code & 4);
+      int most = 0;
+#pragma unroll
+      for (int c8 = 0; c8 < 8; ++c8) {
+        const unsigned long long m = vm & ((c8 & 1) ? b0 : ~b0) & ((c8 & 2) ? b1 : ~b1) & ((c8 & 4) ? b2 : ~b2);
+        const int c = __popcll(m);
+        most = c > most ? c : most;
+      }
+      k.off_mode += (uint32_t)(__popcll(vm) - most);
+    }
+  }
+}
+__device__ __forceinline__ void div_flush(StatLDS& ss, const DivCount& k, int D) {
+  if (__lane_id() == 0 && k.waves) {
+    atomicAdd(&ss.waves, (unsigned long long)k.waves);
+    if (k.waves_div) atomicAdd(&ss.waves_div, (unsigned long long)k.waves_div);
+    if (k.off_mode) atomicAdd(&ss.off_mode, (unsigned long long)k.off_mode);
+    if (k.surv) atomicAdd(&ss.surv[D], (unsigned long long)k.surv);
+  }
+}
+
 __device__ __forceinline__ void div_stats(StatLDS& ss, int D, bool valid, bool surv, int code, bool off_on) {
   const unsigned long long vm = __ballot(valid);
   if (!vm) return;
@@ -826,6 +864,7 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
     uint32_t cnt[NS];
 #pragma unroll
     for (int v = 0; v < NS; ++v) cnt[v] = 0;
+    DivCount dk{0u, 0u, 0u, 0u};
     // state of the lane's last track of the tile (the earlier ones are parked)
     Track<R> t;
     Creations<R> cr;
@@ -850,7 +889,7 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
         lim_code = (surv ? 1 : 0) | (cr.n << 1);
         book(a, lds_tally ? &tl : nullptr, lds_tally ? nullptr : &tc, t.event, v0, dep, t.pos);
       }
-      div_stats(ss, D, valid, surv, lim_code, a.off_mode_on != 0);
+      div_count(dk, valid, surv, lim_code, a.off_mode_on != 0);
       // output counts of this track (constant indices only: the arrays stay in registers)
       if (valid) {
         uint32_t cc[3];
@@ -876,6 +915,7 @@ __global__ void __launch_bounds__(LB) ADEPT_STEP_ATTR k_step(const KArgs a) {
         if (u < TPT - 1) park(pk, threadIdx.x, t, cr, surv, valid, aux);
       }
     }
+    div_flush(ss, dk, D);
     pt.mark(ph_acc, 0);
     uint32_t lex[NS];
     unsigned long long aggw[(NS + 2) / 3];
