@@ -223,12 +223,14 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
          __longlong_as_double((long long)lane_value(u, 63));
 }
 
-// Inclusive scan over the 64 lanes of a wavefront (every lane active).
+// Inclusive scan over the 64 lanes of a wavefront (every lane active): row scans,
+// then the GFX9 row broadcasts (row_bcast:15 adds lane 15 of each row to rows 1
+// and 3, row_bcast:31 adds lane 31 to rows 2 and 3), with no lane reads.
 __device__ __forceinline__ uint32_t wave_scan(uint32_t x) {
   x = row_scan(x);
-  const uint32_t r0 = lane_value(x, 15), r1 = lane_value(x, 31), r2 = lane_value(x, 47);
-  const int row = __lane_id() >> 4;
-  return x + (row >= 1 ? r0 : 0u) + (row >= 2 ? r1 : 0u) + (row >= 3 ? r2 : 0u);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);
+  return x;
 }
 // Sum over the 64 lanes of a wavefront (every lane active); uniform result.
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
