@@ -48,6 +48,9 @@ struct Rec<false> {
   __host__ __device__ static constexpr uint32_t size(int l) { return l < 10 ? 8u : 4u; }
   __host__ __device__ static constexpr uint32_t off(int l) { return l < 10 ? 8u * l : 80u + 4u * (l - 10); }
   __host__ __device__ static constexpr uint32_t prefix(int l) { return off(l); }
+  // 4-byte and 8-byte fields before field l (SoA start offsets)
+  __host__ __device__ static constexpr uint32_t n4(int l) { return l <= 10 ? 0u : (uint32_t)(l - 10); }
+  __host__ __device__ static constexpr uint32_t n8(int l) { return l < 10 ? (uint32_t)l : 10u; }
 };
 
 template <>
@@ -64,11 +67,18 @@ struct Rec<true> {
   __host__ __device__ static constexpr uint32_t prefix(int l) {
     return l < 3 ? 8u * l : (l < 8 ? 24u + 4u * (l - 3) : (l < 10 ? 44u + 8u * (l - 8) : 60u + 4u * (l - 10)));
   }
+  // 4-byte and 8-byte fields before field l (SoA start offsets)
+  __host__ __device__ static constexpr uint32_t n4(int l) {
+    return l <= 3 ? 0u : (l <= 8 ? (uint32_t)(l - 3) : (l <= 10 ? 5u : 5u + (uint32_t)(l - 10)));
+  }
+  __host__ __device__ static constexpr uint32_t n8(int l) { return l <= 3 ? (uint32_t)l : (l <= 8 ? 3u : (l <= 10 ? 3u + (uint32_t)(l - 8) : 5u)); }
 };
 
 // Runtime parameters of one mapping instance (host-computed, passed by value).
 struct MapArgs {
   uint64_t soa_start[14];  // SoA: byte offset of each field array; per type: F(leaf)
+  uint64_t a4, a8;         // SoA: the padded sizes of a 4-byte and of an 8-byte field array
+                           // (soa_start[l] = n4(l) * a4 + n8(l) * a8)
   uint32_t lg;             // AoSoA: log2 N; per type: g
   uint32_t pad;
   uint64_t blk;            // per type: B
@@ -84,6 +94,8 @@ inline MapArgs make_map_args(int map, uint32_t lanes, uint64_t C) {
     m.soa_start[l] = a;
     a = align256(a + C * Rec<MIXED>::size(l));
   }
+  m.a4 = align256(4 * C);
+  m.a8 = align256(8 * C);
   uint32_t lg = 0;
   while ((1u << lg) < lanes) ++lg;
   m.lg = map == MAP_AOSOA ? lg : 0;
@@ -125,7 +137,9 @@ template <int MAP, bool MIXED>
 __host__ __device__ __forceinline__ uint64_t leaf_addr(const MapArgs& m, uint64_t slot, int l) {
   using RC = Rec<MIXED>;
   if (MAP == MAP_AOS) return slot * RC::stride + RC::off(l);
-  if (MAP == MAP_SOA) return m.soa_start[l] + slot * RC::size(l);
+  // two scalars instead of fourteen start offsets (the same values: field arrays
+  // start 256-aligned, so each one's padded size is align256(C * size))
+  if (MAP == MAP_SOA) return RC::n4(l) * m.a4 + RC::n8(l) * m.a8 + slot * RC::size(l);
   if (MAP == MAP_TYPED)
     return (slot >> m.lg) * m.blk + m.soa_start[l] + (slot & ((1ull << m.lg) - 1)) * RC::size(l);
   const uint64_t mask = (1ull << m.lg) - 1;

@@ -92,10 +92,12 @@ def test_philox_and_ids_bitwise(hd, oracle_mod):
         assert hd.hd_child_id(seed, pid, n, kk) == oracle_mod.child_id(seed, pid, n, kk)
 
 
+@pytest.mark.parametrize("capacity", [4096, 1000, 4097])
 @pytest.mark.parametrize("mixed", [0, 1])
 @pytest.mark.parametrize("mapping,lanes", [(0, 1), (1, 1), (2, 2), (2, 16), (2, 64), (2, 256)])
-def test_layouts_match_oracle_byte_map(hd, oracle_mod, mixed, mapping, lanes):
-    C = 4096
+def test_layouts_match_oracle_byte_map(hd, oracle_mod, mixed, mapping, lanes, capacity):
+    """Capacities that are not multiples of 64 pad the SoA field arrays (256-byte starts)."""
+    C = max(lanes, capacity // lanes * lanes)
     assert hd.hd_buffer_bytes(mapping, mixed, lanes, C) == oracle_mod.buffer_bytes(mapping, lanes, mixed, C)
     rng = np.random.default_rng(9)
     for slot in list(rng.integers(0, C, 300)) + [0, C - 1]:
