@@ -22,16 +22,30 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "hostdev", "hostdev.cpp")
 
 
-@pytest.fixture(scope="module")
-def hd(tmp_path_factory):
+def _build_hostdev(tmp_path_factory, defines=()):
     out = str(tmp_path_factory.mktemp("hostdev") / "libhostdev.so")
     try:
         subprocess.check_call(["hipcc", "-x", "hip", "--offload-host-only", "-O2", "-std=c++17", "-ffp-contract=off",
-                               "-fPIC", "-shared", "-o", out, SRC], cwd=str(tmp_path_factory.getbasetemp()),
+                               *[f"-D{d}" for d in defines], "-fPIC", "-shared", "-o", out, SRC],
+                              cwd=str(tmp_path_factory.getbasetemp()),
                               stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
     except (OSError, subprocess.CalledProcessError):
         pytest.skip("hipcc not available")
-    L = ctypes.CDLL(out)
+    return _bind(ctypes.CDLL(out))
+
+
+@pytest.fixture(scope="module")
+def hd(tmp_path_factory):
+    return _build_hostdev(tmp_path_factory)
+
+
+@pytest.fixture(scope="module")
+def hd_per_path(tmp_path_factory):
+    """The model built with ADEPT_RNG_PER_PATH=1: shared random-number blocks drawn on each path."""
+    return _build_hostdev(tmp_path_factory, ["ADEPT_RNG_PER_PATH=1"])
+
+
+def _bind(L):
     P = ctypes.c_void_p
     L.hd_log.restype = L.hd_exp.restype = ctypes.c_double
     L.hd_log.argtypes = L.hd_exp.argtypes = [ctypes.c_double]
@@ -181,6 +195,30 @@ def test_single_step_bitwise(hd, oracle_mod, ptype, mixed):
         n_sec += k - surv.value
     # the sample exercised both outcomes and created secondaries
     assert 0 < n_surv < len(tracks) and n_sec > 50
+
+
+@pytest.mark.parametrize("mixed", [0, 1])
+@pytest.mark.parametrize("ptype", [0, 1, 2])
+def test_random_blocks_per_path_give_the_same_step(hd, hd_per_path, oracle_mod, ptype, mixed):
+    """Drawing the shared Philox blocks once per step (normal build) or on each path that uses
+    them (the comparison build) yields the same step, bit for bit: the hoisting is a code
+    transformation, not a change of the random numbers."""
+    rng = np.random.default_rng(300 + 10 * ptype + mixed)
+    tracks = random_tracks(rng, 1500, ptype, mixed)
+    res = []
+    for L in (hd, hd_per_path):
+        outs = []
+        for t in tracks:
+            tin = np.array([t], dtype=oracle_mod.TRACK_DTYPE)
+            out = np.zeros(4, dtype=oracle_mod.TRACK_DTYPE)
+            out_type = np.zeros(4, dtype=np.int32)
+            dep = np.zeros(5)
+            surv = ctypes.c_int()
+            k = L.hd_step(mixed, ptype, _p(tin), ctypes.byref(surv), _p(out), _p(out_type), _p(dep))
+            outs.append((k, surv.value, out[:k].tobytes(), out_type[:k].tobytes(), dep.tobytes()))
+        res.append(outs)
+    assert res[0] == res[1]
+    assert sum(o[0] - o[1] for o in res[0]) > 50  # creations were exercised
 
 
 def test_distance_with_skipped_divisions_is_exact(hd, oracle_mod):
