@@ -66,7 +66,12 @@ AD_HD U4 philox(U4 c, uint32_t k0, uint32_t k1) {
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
-    const U4 n = {xor3((uint32_t)(p1 >> 32), c.y, k0), (uint32_t)p1, xor3((uint32_t)(p0 >> 32), c.w, k1), (uint32_t)p0};
+    // fully unrolled, the first round's counter words are often constants (block
+    // index, zero) that plain XORs fold; the three-input form takes registers only
+    const bool fold = U == 10 && r == 0;
+    const uint32_t h1 = (uint32_t)(p1 >> 32), h0 = (uint32_t)(p0 >> 32);
+    const U4 n = {fold ? (h1 ^ c.y ^ k0) : xor3(h1, c.y, k0), (uint32_t)p1, fold ? (h0 ^ c.w ^ k1) : xor3(h0, c.w, k1),
+                  (uint32_t)p0};
     c = n;
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
